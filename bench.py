@@ -1,0 +1,135 @@
+"""Benchmark: reachable pairs per second of the Kronecker-product fixpoint on
+one MI355X.
+
+Workload (one "step" = one whole query, every step of the hot path):
+  regular path query (a|b)* c d* compiled to its minimal 2-state automaton,
+  on a seeded power-law directed graph, n = 100,000, out-degrees
+  round(Pareto(2.1)) with mean 4, uniform targets, labels Zipf(1.2) over
+  {a, b, c, d}.  The graph is resident in HBM before timing starts, as the
+  paper excludes graph loading from its timings.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel (one frontier level of the incremental closure, HBM-bound), and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--tile-words", type=int, default=0)
+    ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
+              f"described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2103_14688_amd import cfpq, rsm
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    g = synth.powerlaw(args.n, seed=synth.BASE_SEED + 2)
+    R = rsm.from_regex(synth.RPQ_C2, g.labels)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    kw = dict(strategy=cfpq.STRATEGY_LEVELS, tile_words=args.tile_words)
+    print(f"# graph n={g.n} m={len(g.src)} states={R.n_states}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        cfpq.query(graph, q, **kw).close()
+    torch.cuda.synchronize()
+
+    results = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(cfpq.query(graph, q, profile=True, **kw))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    pairs = results[-1].count(0)
+    it, deltas, fix_ms = results[-1].stats()
+    fix = [r.stats()[2] for r in results]
+    # dominant kernel: closure level launches, summed over the timed steps
+    lv_n = lv_ms = lv_bytes = 0
+    for r in results:
+        n_l, ms_l, by_l = r.profile(cfpq.KERNEL_LEVEL)
+        lv_n += n_l
+        lv_ms += ms_l
+        lv_bytes += by_l
+    seed = [r.profile(cfpq.KERNEL_SEED) for r in results]
+    wb = [r.profile(cfpq.KERNEL_WRITEBACK) for r in results]
+    for r in results:
+        r.close()
+    avg_launch_ms = lv_ms / max(lv_n, 1)
+    bytes_per_launch = lv_bytes / max(lv_n, 1)
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        rng = np.random.default_rng(synth.BASE_SEED + 7)
+        srcs = np.sort(rng.choice(g.n, size=min(args.cpu_sources, g.n), replace=False)).astype(np.uint32)
+        tc = time.perf_counter()
+        rows = oracle.rpq_rows(g.n, g.src, g.lbl, g.dst, g.labels, synth.RPQ_C2, srcs, threads=threads)
+        dt = time.perf_counter() - tc
+        cpu_pairs = int(np.unpackbits(rows.view(np.uint8)).sum())
+        cpu = {"value": cpu_pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(srcs)} of {g.n} sources (product-automaton BFS per source), "
+                         f"{cpu_pairs} pairs in {dt:.2f} s"}
+
+    out = {
+        "metric": "reachable pairs/s (fixpoint, plain single query)",
+        "value": pairs * args.steps / wall,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"RPQ (a|b)* c d* on power-law graph n={g.n} (Pareto(2.1) out-degree mean 4, "
+                        f"Zipf(1.2) labels), plain one-query-at-a-time path",
+            "n": g.n, "edges": int(len(g.src)), "rsm_states": int(R.n_states), "pairs": int(pairs),
+            "iterations": it, "fixpoint_ms_median": float(np.median(fix)), "fixpoint_ms_mean": float(np.mean(fix)),
+            "tile_words": args.tile_words,
+            "level_launches_per_step": lv_n / args.steps,
+            "seed_ms_per_step": sum(s[1] for s in seed) / args.steps,
+            "writeback_ms_per_step": sum(w[1] for w in wb) / args.steps,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_gather<false> (closure frontier level)",
+            "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * cfpq.h -- C ABI of the MI355X (gfx950) Kronecker-product path-query library.
+ *
+ * The library evaluates context-free and regular path queries with the
+ * index-creation fixpoint of Shemetova et al., "One Algorithm to Evaluate
+ * Them All" (Sec. 3.1, Listing 1): the Kronecker product of the query's
+ * recursive-state-machine matrices with the graph's label matrices, the
+ * incremental transitive closure of the product, and the write-back of new
+ * nonterminal edges into the graph, repeated until no edge is added.
+ *
+ * Conventions for every call:
+ *   - Every call returns cfpq_status; CFPQ_OK (0) on success.  No C++
+ *     exception crosses this boundary.  cfpq_last_error() returns a
+ *     thread-local text for the last non-OK status of the calling thread.
+ *   - Inputs are caller-owned and copied during the call; the library keeps
+ *     no pointer to caller memory.  Handles are library-owned until their
+ *     destroy call.  Output buffers are caller-owned.
+ *   - Vertex ids are 0..n-1, label ids 0..n_labels-1 (uint32).
+ *   - A bitmap over pairs is row-major: row u holds ceil(n/64) uint64 words,
+ *     bit (v % 64) of word (v / 64) set iff (u, v) is in the relation;
+ *     bits at v >= n are zero.
+ *   - Handles are immutable after creation: queries on different streams
+ *     may share a graph and an RSM.  A result must not be destroyed while
+ *     another thread uses it.
+ *   - Device memory comes from the optional allocator (e.g. PyTorch's caching
+ *     allocator), else from hipMalloc.  "stream" arguments are hipStream_t
+ *     values passed as void* (NULL = the null stream).
+ */
+#ifndef CFPQ_H
+#define CFPQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CFPQ_OK = 0,
+    CFPQ_ERR_INVALID = -1,   /* an argument violates the rules stated below */
+    CFPQ_ERR_OOM = -2,       /* device or host allocation failed */
+    CFPQ_ERR_DEVICE = -3,    /* a HIP runtime call or kernel launch failed */
+    CFPQ_ERR_NOT_FOUND = -4, /* extract_path: the pair is not in the relation */
+    CFPQ_ERR_BUFFER = -5,    /* output buffer too small; required size returned */
+    CFPQ_ERR_LIMIT = -6,     /* an iteration/size limit of the call was reached */
+    CFPQ_ERR_REJECTED = -7   /* the request does not fit the resources given */
+} cfpq_status;
+
+typedef struct cfpq_graph_s *cfpq_graph;
+typedef struct cfpq_rsm_s *cfpq_rsm;
+typedef struct cfpq_result_s *cfpq_result;
+
+/* Device-memory hooks.  alloc returns NULL on failure; free receives the
+ * pointer and size that alloc produced.  Both are called with the stream the
+ * memory is used on. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
+    void *ctx;
+} cfpq_allocator;
+
+/* ------------------------------------------------------------------------
+ * Graph: an edge-labelled directed graph <V, E, L> (Sec. 2.1, definition of
+ * an edge-labelled graph) held as its Boolean decomposition, one Boolean
+ * matrix per label (Sec. 2.1, Boolean matrices decomposition).  On the
+ * device each label matrix is stored by columns: for every vertex v the
+ * sorted, duplicate-free list of its predecessors under that label.
+ *
+ * n_vertices >= 1; n_labels >= 1; src/label/dst: n_edges host arrays.
+ * E is a set: duplicate edges collapse; self-loops are kept.
+ * flags: CFPQ_ADD_INVERSES adds, for every label l, the inverse label
+ *   n_labels + l carrying (v, u) for each (u, l, v) (the inverse relation of
+ *   the same-generation and alias queries, Sec. 4.2); the graph then has
+ *   2 * n_labels labels.
+ * Errors: CFPQ_ERR_INVALID if n_vertices == 0, n_labels == 0, a vertex
+ *   >= n_vertices, a label >= n_labels, a NULL array with n_edges > 0, or
+ *   more than 2^32 - 1 distinct edges.
+ * The graph stays resident on the current device until cfpq_graph_destroy.
+ * ---------------------------------------------------------------------- */
+#define CFPQ_ADD_INVERSES 1u
+
+cfpq_status cfpq_graph_create(uint32_t n_vertices, uint32_t n_labels, const uint32_t *src,
+                              const uint32_t *label, const uint32_t *dst, uint64_t n_edges,
+                              uint32_t flags, const cfpq_allocator *alloc, void *stream,
+                              cfpq_graph *out);
+cfpq_status cfpq_graph_info(cfpq_graph g, uint32_t *n_vertices, uint32_t *n_labels,
+                            uint64_t *n_edges);
+void cfpq_graph_destroy(cfpq_graph g);
+
+/* ------------------------------------------------------------------------
+ * Recursive state machine (Sec. 2.3, definition of an RSM): boxes with
+ * pairwise disjoint state sets, one initial state each, a set of final
+ * states each, and transitions over terminals and box labels.  A regular
+ * path query is a one-box RSM with no box-labelled transition (Sec. 3.1.2).
+ *
+ * n_states states 0..n_states-1; n_boxes boxes 0..n_boxes-1.
+ * box_start[b]   : initial state of box b.
+ * state_box[q]   : the box owning state q (state sets are disjoint).
+ * is_final[q]    : nonzero iff q is a final state of its box.
+ * transitions (t_src[i], t_sym[i], t_dst[i]), i < n_trans:
+ *   t_sym <  n_terminals : terminal, matched against graph label t_sym;
+ *   t_sym >= n_terminals : box label (nonterminal) t_sym - n_terminals.
+ * start_box      : the box whose relation is "the answer" (the grammar's
+ *                  start nonterminal); every box's relation is computed.
+ * Errors: CFPQ_ERR_INVALID if a count is zero, an index is out of range, a
+ *   box start is owned by another box, or a transition crosses boxes.
+ * The RSM may be nondeterministic; the relation does not depend on that.
+ * ---------------------------------------------------------------------- */
+cfpq_status cfpq_rsm_create(uint32_t n_states, uint32_t n_terminals, uint32_t n_boxes,
+                            const uint32_t *box_start, const uint32_t *state_box,
+                            const uint8_t *is_final, const uint32_t *t_src, const uint32_t *t_sym,
+                            const uint32_t *t_dst, uint32_t n_trans, uint32_t start_box,
+                            cfpq_rsm *out);
+void cfpq_rsm_destroy(cfpq_rsm r);
+
+/* ------------------------------------------------------------------------
+ * Query: the index-creation fixpoint (Sec. 3.1, Listing 1) on one GPU.
+ *
+ *   a. epsilon initialisation: every box whose initial state is final gets
+ *      all loops (v, v) (Listing 1, before the loop); these loops also count
+ *      as new edges of the first iteration;
+ *   b. each iteration: Kronecker product of the RSM matrices with the NEW
+ *      graph edges only (left-distributivity, Sec. 3.1.1), incremental
+ *      transitive closure of the product restricted to the rows that start
+ *      at a box's initial state, write-back of new nonterminal edges;
+ *   c. stop after the first iteration that adds no nonterminal edge.
+ *
+ * Options (NULL = defaults):
+ *   strategy   : CFPQ_STRATEGY_AUTO, _LEVELS (one launch per closure level,
+ *                any size), _FUSED (one workgroup runs the whole fixpoint;
+ *                small graphs only, CFPQ_ERR_LIMIT beyond its size limit).
+ *   max_iters  : 0 = no limit beyond the natural bound; otherwise the query
+ *                fails with CFPQ_ERR_LIMIT if the loop has not stopped after
+ *                max_iters iterations.
+ *   keep_rank  : keep, for every nonterminal pair, the iteration that added
+ *                it; required by cfpq_extract_path (n <= 16384).
+ *   keep_blocks: keep the closure blocks, required by cfpq_result_block.
+ *   tile_words : source-tile width in 64-bit words (0 = automatic).
+ *   profile    : record HIP events around every launch of the levels
+ *                strategy (see cfpq_result_profile); adds ~1 us per launch.
+ *   stream     : hipStream_t for all work of the call (NULL = null stream).
+ * The call returns after the fixpoint has finished on the device.
+ * Errors: CFPQ_ERR_INVALID if the RSM uses more terminals than the graph
+ *   has labels; CFPQ_ERR_OOM; CFPQ_ERR_DEVICE; CFPQ_ERR_LIMIT.
+ * ---------------------------------------------------------------------- */
+enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2 };
+
+typedef struct {
+    uint32_t strategy;
+    uint32_t max_iters;
+    uint32_t keep_rank;
+    uint32_t keep_blocks;
+    uint32_t tile_words;
+    uint32_t profile;
+    void *stream;
+    const cfpq_allocator *alloc;
+} cfpq_query_opts;
+
+cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opts *opts, cfpq_result *out);
+
+/* Batched query: k (graph, RSM) pairs evaluated together; small queries
+ * share launches (one workgroup per query), the others run one after the
+ * other.  results[i] receives the result of pair i; on error every result
+ * created so far is destroyed and all results[i] are NULL.  The answers are
+ * identical to k separate cfpq_query calls. */
+cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm *rsms, uint32_t k,
+                             const cfpq_query_opts *opts, cfpq_result *results);
+
+/* ------------------------------------------------------------------------
+ * Result accessors.  "box" selects a nonterminal; its relation is the set
+ * of (u, v) such that some path u..v spells a word the box derives
+ * (Theorem 1).
+ * ---------------------------------------------------------------------- */
+/* number of pairs */
+cfpq_status cfpq_result_count(cfpq_result res, uint32_t box, uint64_t *pairs);
+/* order-independent hash: sum over pairs of splitmix64((u << 32) | v) mod 2^64
+ * (SplitMix64 of Steele, Lea and Flood, 2014) */
+cfpq_status cfpq_result_hash(cfpq_result res, uint32_t box, uint64_t *hash);
+/* the relation as a row-major bitmap (see conventions); dst_words must be at
+ * least n * ceil(n/64), else CFPQ_ERR_BUFFER.  dst_on_device != 0: dst is a
+ * device pointer on the result's device. */
+cfpq_status cfpq_result_bitmap(cfpq_result res, uint32_t box, uint64_t *dst, uint64_t dst_words,
+                               int dst_on_device);
+/* the relation as (u, v) pairs, sorted by u then v, into uv[2 * cap_pairs];
+ * *n_pairs receives the count; CFPQ_ERR_BUFFER if cap_pairs is too small. */
+cfpq_status cfpq_result_pairs(cfpq_result res, uint32_t box, uint32_t *uv, uint64_t cap_pairs,
+                              uint64_t *n_pairs);
+/* closure block between an initial state q_start and a state q_final of the
+ * same box (for a regular query: the start/final state pair of the
+ * automaton): bit (u, v) set iff (q_start, u) reaches (q_final, v) in the
+ * product graph by a path of length >= 1, or (u == v and q_start ==
+ * q_final).  Requires keep_blocks.  Row-major bitmap as above. */
+cfpq_status cfpq_result_block(cfpq_result res, uint32_t q_start, uint32_t q_final, uint64_t *dst,
+                              uint64_t dst_words);
+/* iterations of the loop (including the last, unproductive one), new
+ * nonterminal edges per iteration (first min(cap, iterations) entries), and
+ * the device time of the fixpoint in milliseconds (events on the query
+ * stream, from the first kernel to the last). */
+cfpq_status cfpq_result_stats(cfpq_result res, uint32_t *iterations, uint64_t *delta_per_iter,
+                              uint32_t cap, double *fixpoint_ms);
+
+/* ------------------------------------------------------------------------
+ * One witness path for (u, v) in box's relation (Sec. 3.2: a single path can
+ * always be extracted).  Requires keep_rank.  edges receives 3 * n_edges
+ * uint32 values (src, label, dst) in path order; an empty path (u == v, box
+ * nullable) has n_edges == 0.  Each nonterminal edge is expanded through
+ * edges added in strictly earlier iterations, so the expansion terminates.
+ * CFPQ_ERR_NOT_FOUND if (u, v) is not in the relation; CFPQ_ERR_BUFFER with
+ * *n_edges set to the required count if cap_edges is too small;
+ * CFPQ_ERR_LIMIT if the witness exceeds 2^26 edges.
+ * ---------------------------------------------------------------------- */
+cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_t v,
+                              uint32_t *edges, uint64_t cap_edges, uint64_t *n_edges);
+
+/* Per-kernel profile of a query run with opts.profile (levels strategy).
+ * kind: CFPQ_KERNEL_SEED (Kronecker product with the new edges),
+ * CFPQ_KERNEL_LEVEL (one frontier level of the incremental closure) or
+ * CFPQ_KERNEL_WRITEBACK.  launches: number of launches of that kernel;
+ * ms: their summed device time (HIP events on the query stream, between
+ * consecutive launches); bytes: the algorithmic bytes they had to move --
+ * for a level launch 8 * tile_words * (R_in + 3 * R_out), R_in the frontier
+ * rows read and R_out the target rows fed by them (read T, write T and the
+ * next frontier); for a write-back 8 * ceil(n/64) * (|F_N| + 3) per row of
+ * each box.  CFPQ_ERR_INVALID if the query was not profiled. */
+enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2 };
+cfpq_status cfpq_result_profile(cfpq_result res, uint32_t kind, uint64_t *launches, double *ms,
+                                uint64_t *bytes);
+
+void cfpq_result_destroy(cfpq_result res);
+
+const char *cfpq_last_error(void);
+
+/* Library version string. */
+const char *cfpq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFPQ_H */

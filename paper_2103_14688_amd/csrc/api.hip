@@ -1,0 +1,1130 @@
+// Host side of the C ABI declared in include/cfpq.h: validation, graph and
+// RSM staging, the fixpoint driver (Sec. 3.1, Listing 1), result accessors
+// and single-witness extraction (Sec. 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cfpq.h"
+#include "internal.h"
+
+using namespace cfpq;
+
+namespace {
+
+thread_local std::string g_err;
+
+cfpq_status fail(cfpq_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(CFPQ_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory through the optional allocator hooks
+// ---------------------------------------------------------------------------
+struct Alloc {
+    cfpq_allocator a{};
+    bool has = false;
+    explicit Alloc(const cfpq_allocator *p = nullptr) {
+        if (p && p->alloc && p->free) {
+            a = *p;
+            has = true;
+        }
+    }
+    void *get(size_t bytes, hipStream_t s) const {
+        if (!bytes) bytes = 8;
+        if (has) return a.alloc(bytes, (void *)s, a.ctx);
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void *p, size_t bytes, hipStream_t s) const {
+        if (!p) return;
+        if (!bytes) bytes = 8;
+        if (has)
+            a.free(p, bytes, (void *)s, a.ctx);
+        else
+            (void)hipFree(p);
+    }
+};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    const Alloc *al = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        release();
+        p = o.p; bytes = o.bytes; al = o.al; s = o.s;
+        o.p = nullptr; o.bytes = 0;
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void release() {
+        if (p && al) al->put(p, bytes, s);
+        p = nullptr;
+        bytes = 0;
+    }
+    bool alloc(const Alloc *a, size_t nbytes, hipStream_t st) {
+        release();
+        al = a; s = st; bytes = nbytes ? nbytes : 8;
+        p = a->get(bytes, st);
+        return p != nullptr;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct cfpq_graph_s {
+    int device = 0;
+    uint32_t n = 0, n_labels = 0;
+    uint64_t n_edges = 0;
+    Alloc alloc;
+    DevBuf off, idx;                         // CSC per label (predecessors)
+    std::vector<uint32_t> h_out_off, h_out;  // CSR per label (successors), host
+};
+
+struct cfpq_rsm_s {
+    uint32_t n_states = 0, n_terms = 0, n_boxes = 0, start_box = 0;
+    std::vector<uint32_t> box_start, state_box, t_src, t_sym, t_dst;
+    std::vector<uint8_t> is_final;
+};
+
+struct cfpq_result_s {
+    int device = 0;
+    uint32_t n = 0, P = 0, Pn = 0, nB = 0, nQ = 0;
+    hipStream_t stream = nullptr;
+    Alloc alloc;
+    DevBuf NT;        // [nB][n][P] transposed nonterminal matrices
+    DevBuf T;         // [nQ][n][P] closure rows (keep_blocks)
+    DevBuf rank;      // [nB][n][n] u8 (keep_rank)
+    DevBuf scratch;   // small device scratch for accessors
+    uint32_t iterations = 0;
+    std::vector<uint64_t> deltas;
+    double ms = 0.0;
+    cfpq_rsm_s rsm;                              // copy
+    std::vector<uint32_t> out_off, out;          // graph successors (keep_rank only)
+    uint32_t n_labels = 0;
+    std::vector<uint8_t> h_rank;                 // lazily fetched, [N][u][v]
+    struct Prof {
+        uint64_t launches = 0, bytes = 0;
+        double ms = 0.0;
+    } prof[3];
+    bool profiled = false;
+};
+
+// ---------------------------------------------------------------------------
+// graph
+// ---------------------------------------------------------------------------
+extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const uint32_t *src,
+                                         const uint32_t *label, const uint32_t *dst,
+                                         uint64_t n_edges, uint32_t flags,
+                                         const cfpq_allocator *alloc, void *stream,
+                                         cfpq_graph *out) {
+    if (!out) return fail(CFPQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n == 0 || n_labels == 0) return fail(CFPQ_ERR_INVALID, "graph needs n_vertices >= 1 and n_labels >= 1");
+    if (n_edges && (!src || !label || !dst)) return fail(CFPQ_ERR_INVALID, "edge array is NULL");
+    if (flags & ~CFPQ_ADD_INVERSES) return fail(CFPQ_ERR_INVALID, "unknown flag");
+    if (n == 0xFFFFFFFFu) return fail(CFPQ_ERR_INVALID, "too many vertices");
+    const bool inv = flags & CFPQ_ADD_INVERSES;
+    const uint32_t L = inv ? 2 * n_labels : n_labels;
+    if (inv && n_labels > 0x7FFFFFFFu) return fail(CFPQ_ERR_INVALID, "too many labels");
+    struct E { uint32_t l, d, s; };
+    std::vector<E> e;
+    try {
+        e.reserve(inv ? 2 * n_edges : n_edges);
+    } catch (...) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    for (uint64_t i = 0; i < n_edges; ++i) {
+        if (src[i] >= n || dst[i] >= n) return fail(CFPQ_ERR_INVALID, "edge " + std::to_string(i) + ": vertex out of range");
+        if (label[i] >= n_labels) return fail(CFPQ_ERR_INVALID, "edge " + std::to_string(i) + ": label out of range");
+        e.push_back({label[i], dst[i], src[i]});
+        if (inv) e.push_back({label[i] + n_labels, src[i], dst[i]});
+    }
+    std::sort(e.begin(), e.end(), [](const E &a, const E &b) {
+        if (a.l != b.l) return a.l < b.l;
+        if (a.d != b.d) return a.d < b.d;
+        return a.s < b.s;
+    });
+    e.erase(std::unique(e.begin(), e.end(), [](const E &a, const E &b) {
+                return a.l == b.l && a.d == b.d && a.s == b.s;
+            }),
+            e.end());
+    if (e.size() >= 0xFFFFFFFFull) return fail(CFPQ_ERR_INVALID, "more than 2^32-1 distinct edges");
+
+    std::unique_ptr<cfpq_graph_s> g(new (std::nothrow) cfpq_graph_s);
+    if (!g) return fail(CFPQ_ERR_OOM, "host allocation failed");
+    HIP_TRY(hipGetDevice(&g->device));
+    g->n = n;
+    g->n_labels = L;
+    g->n_edges = e.size();
+    g->alloc = Alloc(alloc);
+    hipStream_t s = (hipStream_t)stream;
+
+    const uint64_t noff = (uint64_t)L * (n + 1);
+    std::vector<uint32_t> off(noff, 0), idx(e.size());
+    try {
+        g->h_out_off.assign(noff, 0);
+        g->h_out.resize(e.size());
+    } catch (...) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    for (const E &x : e) {
+        off[(uint64_t)x.l * (n + 1) + x.d + 1]++;
+        g->h_out_off[(uint64_t)x.l * (n + 1) + x.s + 1]++;
+    }
+    // offsets are global across labels: label l's lists start where l-1's end
+    uint64_t run = 0, run2 = 0;
+    for (uint32_t l = 0; l < L; ++l) {
+        uint32_t *o = &off[(uint64_t)l * (n + 1)];
+        uint32_t *o2 = &g->h_out_off[(uint64_t)l * (n + 1)];
+        o[0] = (uint32_t)run;
+        o2[0] = (uint32_t)run2;
+        for (uint32_t v = 0; v < n; ++v) {
+            run += o[v + 1];
+            o[v + 1] = (uint32_t)run;
+            run2 += o2[v + 1];
+            o2[v + 1] = (uint32_t)run2;
+        }
+    }
+    for (uint64_t i = 0; i < e.size(); ++i) idx[i] = e[i].s;  // sorted by (l, d, s)
+    {
+        std::vector<uint32_t> fill(g->h_out_off.begin(), g->h_out_off.end());
+        for (const E &x : e) g->h_out[fill[(uint64_t)x.l * (n + 1) + x.s]++] = x.d;
+        for (uint32_t l = 0; l < L; ++l)
+            for (uint32_t u = 0; u < n; ++u) {
+                uint64_t a = g->h_out_off[(uint64_t)l * (n + 1) + u], b = g->h_out_off[(uint64_t)l * (n + 1) + u + 1];
+                std::sort(g->h_out.begin() + a, g->h_out.begin() + b);
+            }
+    }
+    if (!g->off.alloc(&g->alloc, noff * sizeof(uint32_t), s) ||
+        !g->idx.alloc(&g->alloc, idx.size() * sizeof(uint32_t), s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (graph)");
+    HIP_TRY(hipMemcpyAsync(g->off.p, off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (!idx.empty())
+        HIP_TRY(hipMemcpyAsync(g->idx.p, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = g.release();
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_graph_info(cfpq_graph g, uint32_t *n, uint32_t *n_labels, uint64_t *n_edges) {
+    if (!g) return fail(CFPQ_ERR_INVALID, "graph is NULL");
+    if (n) *n = g->n;
+    if (n_labels) *n_labels = g->n_labels;
+    if (n_edges) *n_edges = g->n_edges;
+    return CFPQ_OK;
+}
+
+extern "C" void cfpq_graph_destroy(cfpq_graph g) { delete g; }
+
+// ---------------------------------------------------------------------------
+// RSM
+// ---------------------------------------------------------------------------
+extern "C" cfpq_status cfpq_rsm_create(uint32_t n_states, uint32_t n_terminals, uint32_t n_boxes,
+                                       const uint32_t *box_start, const uint32_t *state_box,
+                                       const uint8_t *is_final, const uint32_t *t_src,
+                                       const uint32_t *t_sym, const uint32_t *t_dst,
+                                       uint32_t n_trans, uint32_t start_box, cfpq_rsm *out) {
+    if (!out) return fail(CFPQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_states == 0 || n_boxes == 0) return fail(CFPQ_ERR_INVALID, "RSM needs states and boxes");
+    if (!box_start || !state_box || !is_final) return fail(CFPQ_ERR_INVALID, "RSM array is NULL");
+    if (n_trans && (!t_src || !t_sym || !t_dst)) return fail(CFPQ_ERR_INVALID, "transition array is NULL");
+    if (start_box >= n_boxes) return fail(CFPQ_ERR_INVALID, "start_box out of range");
+    if ((uint64_t)n_terminals + n_boxes > 0xFFFFFFFFull) return fail(CFPQ_ERR_INVALID, "too many symbols");
+    for (uint32_t q = 0; q < n_states; ++q)
+        if (state_box[q] >= n_boxes) return fail(CFPQ_ERR_INVALID, "state_box out of range");
+    for (uint32_t b = 0; b < n_boxes; ++b) {
+        if (box_start[b] >= n_states) return fail(CFPQ_ERR_INVALID, "box_start out of range");
+        if (state_box[box_start[b]] != b) return fail(CFPQ_ERR_INVALID, "box start owned by another box");
+    }
+    for (uint32_t i = 0; i < n_trans; ++i) {
+        if (t_src[i] >= n_states || t_dst[i] >= n_states) return fail(CFPQ_ERR_INVALID, "transition state out of range");
+        if (t_sym[i] >= n_terminals + n_boxes) return fail(CFPQ_ERR_INVALID, "transition symbol out of range");
+        if (state_box[t_src[i]] != state_box[t_dst[i]]) return fail(CFPQ_ERR_INVALID, "transition crosses boxes");
+    }
+    std::unique_ptr<cfpq_rsm_s> r(new (std::nothrow) cfpq_rsm_s);
+    if (!r) return fail(CFPQ_ERR_OOM, "host allocation failed");
+    r->n_states = n_states; r->n_terms = n_terminals; r->n_boxes = n_boxes; r->start_box = start_box;
+    r->box_start.assign(box_start, box_start + n_boxes);
+    r->state_box.assign(state_box, state_box + n_states);
+    r->is_final.resize(n_states);
+    for (uint32_t q = 0; q < n_states; ++q) r->is_final[q] = is_final[q] ? 1 : 0;
+    // a transition is a set element: drop duplicates
+    std::vector<std::array<uint32_t, 3>> tr;
+    for (uint32_t i = 0; i < n_trans; ++i) tr.push_back({t_src[i], t_sym[i], t_dst[i]});
+    std::sort(tr.begin(), tr.end());
+    tr.erase(std::unique(tr.begin(), tr.end()), tr.end());
+    for (auto &t : tr) {
+        r->t_src.push_back(t[0]); r->t_sym.push_back(t[1]); r->t_dst.push_back(t[2]);
+    }
+    *out = r.release();
+    return CFPQ_OK;
+}
+
+extern "C" void cfpq_rsm_destroy(cfpq_rsm r) { delete r; }
+
+// ---------------------------------------------------------------------------
+// query planning shared by both strategies
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr uint32_t kFusedMaxN = 2048;
+constexpr uint32_t kFusedMaxBoxesHost = 64;
+constexpr uint32_t kStatsCap = 4096;
+
+struct Plan {
+    uint32_t n, Pn, P, nQ, nB, n_terms;
+    std::vector<uint32_t> in_off;
+    std::vector<InTrans> in_tr;
+    std::vector<uint32_t> starts;     // box start per box
+    std::vector<uint32_t> fin_off, fin;
+    std::vector<uint32_t> eps_boxes;  // boxes whose start is final
+    std::vector<uint8_t> nullable, box_used;
+};
+
+Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
+    Plan p;
+    p.n = g.n;
+    p.Pn = (g.n + 63) / 64;
+    p.P = round_up(p.Pn, 8);
+    p.nQ = r.n_states;
+    p.nB = r.n_boxes;
+    p.n_terms = r.n_terms;
+    p.in_off.assign(p.nQ + 1, 0);
+    for (size_t i = 0; i < r.t_src.size(); ++i) p.in_off[r.t_dst[i] + 1]++;
+    for (uint32_t q = 0; q < p.nQ; ++q) p.in_off[q + 1] += p.in_off[q];
+    p.in_tr.resize(r.t_src.size());
+    std::vector<uint32_t> fill(p.in_off.begin(), p.in_off.end() - 1);
+    for (size_t i = 0; i < r.t_src.size(); ++i) p.in_tr[fill[r.t_dst[i]]++] = InTrans{r.t_src[i], r.t_sym[i]};
+    p.starts = r.box_start;
+    p.fin_off.assign(p.nB + 1, 0);
+    for (uint32_t q = 0; q < p.nQ; ++q)
+        if (r.is_final[q]) p.fin_off[r.state_box[q] + 1]++;
+    for (uint32_t b = 0; b < p.nB; ++b) p.fin_off[b + 1] += p.fin_off[b];
+    p.fin.resize(p.fin_off[p.nB]);
+    std::vector<uint32_t> ff(p.fin_off.begin(), p.fin_off.end() - 1);
+    for (uint32_t q = 0; q < p.nQ; ++q)
+        if (r.is_final[q]) p.fin[ff[r.state_box[q]]++] = q;
+    p.nullable.assign(p.nB, 0);
+    p.box_used.assign(p.nB, 0);
+    for (uint32_t b = 0; b < p.nB; ++b)
+        if (r.is_final[r.box_start[b]]) {
+            p.nullable[b] = 1;
+            p.eps_boxes.push_back(b);
+        }
+    for (size_t i = 0; i < r.t_sym.size(); ++i)
+        if (r.t_sym[i] >= r.n_terms) p.box_used[r.t_sym[i] - r.n_terms] = 1;
+    return p;
+}
+
+// device copy of the small per-query tables
+struct Tables {
+    DevBuf buf;
+    uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
+             *eps = nullptr;
+    InTrans *in_tr = nullptr;
+    uint8_t *nullable = nullptr, *box_used = nullptr;
+};
+
+cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
+    std::vector<uint8_t> host;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t at = (host.size() + 15) / 16 * 16;
+        host.resize(at + bytes + 16);
+        if (bytes) std::memcpy(host.data() + at, src, bytes);
+        return at;
+    };
+    size_t o_in_off = put(p.in_off.data(), p.in_off.size() * 4);
+    size_t o_in_tr = put(p.in_tr.data(), p.in_tr.size() * sizeof(InTrans));
+    size_t o_starts = put(p.starts.data(), p.starts.size() * 4);
+    size_t o_fin_off = put(p.fin_off.data(), p.fin_off.size() * 4);
+    size_t o_fin = put(p.fin.data(), p.fin.size() * 4);
+    size_t o_eps = put(p.eps_boxes.data(), p.eps_boxes.size() * 4);
+    size_t o_null = put(p.nullable.data(), p.nullable.size());
+    size_t o_used = put(p.box_used.data(), p.box_used.size());
+    if (!t.buf.alloc(al, host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
+    HIP_TRY(hipMemcpyAsync(t.buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
+    uint8_t *b = t.buf.as<uint8_t>();
+    t.in_off = (uint32_t *)(b + o_in_off);
+    t.in_tr = (InTrans *)(b + o_in_tr);
+    t.starts = (uint32_t *)(b + o_starts);
+    t.fin_off = (uint32_t *)(b + o_fin_off);
+    t.fin = (uint32_t *)(b + o_fin);
+    t.eps = (uint32_t *)(b + o_eps);
+    t.nullable = b + o_null;
+    t.box_used = b + o_used;
+    // the host vector dies with this frame: wait for the copy
+    HIP_TRY(hipStreamSynchronize(s));
+    return CFPQ_OK;
+}
+
+cfpq_status check_pair(const cfpq_graph_s *g, const cfpq_rsm_s *r) {
+    if (!g || !r) return fail(CFPQ_ERR_INVALID, "graph or RSM is NULL");
+    if (r->n_terms > g->n_labels)
+        return fail(CFPQ_ERR_INVALID, "RSM uses more terminals than the graph has labels");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != g->device) return fail(CFPQ_ERR_INVALID, "graph lives on another device");
+    return CFPQ_OK;
+}
+
+struct PinnedCounters {
+    unsigned long long *h = nullptr;
+    size_t cap = 0;
+    ~PinnedCounters() {
+        if (h) (void)hipHostFree(h);
+    }
+    bool ensure(size_t n) {
+        if (n <= cap) return true;
+        if (h) (void)hipHostFree(h);
+        h = nullptr;
+        cap = 0;
+        if (hipHostMalloc((void **)&h, n * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) return false;
+        cap = n;
+        return true;
+    }
+};
+
+uint32_t gather_grid(uint64_t rows) {
+    uint64_t blocks = (rows + (kBlock / kWave) - 1) / (kBlock / kWave);
+    const uint64_t cap = 256 * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    return (uint32_t)blocks;
+}
+
+// ---------------------------------------------------------------------------
+// LEVELS strategy: one launch per closure level, any graph size
+// ---------------------------------------------------------------------------
+cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o,
+                       cfpq_result_s &res) {
+    hipStream_t s = (hipStream_t)o.stream;
+    const Alloc *al = &res.alloc;
+    Plan p = make_plan(g, r);
+    Tables tb;
+    cfpq_status st = upload_tables(p, al, s, tb);
+    if (st != CFPQ_OK) return st;
+
+    const uint32_t n = p.n, P = p.P, Pn = p.Pn, nQ = p.nQ, nB = p.nB;
+    uint32_t G = o.tile_words ? std::min<uint32_t>(o.tile_words, Pn) : Pn;
+    if (G == 0) G = 1;
+    const uint32_t groups = (Pn + G - 1) / G;
+    const uint64_t qw = (uint64_t)nQ * n * P, bw = (uint64_t)nB * n * P, fw = (uint64_t)nQ * n * G;
+    const uint64_t aw = (uint64_t)nQ * Pn;
+    const uint64_t ring_words = (uint64_t)kRingSlots * kSlotWords;
+
+    DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr;
+    if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
+        !D0.alloc(al, fw * 8, s) || !D1.alloc(al, fw * 8, s) || !acts.alloc(al, 3 * aw * 8, s) ||
+        !tnz.alloc(al, aw * 8, s) || !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) ||
+        !ctr.alloc(al, ring_words * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (query state)");
+    if (o.keep_rank) {
+        if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
+        HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)nB * n * n, s));  // 0xFF = absent
+    }
+    uint64_t *d_T = T.as<uint64_t>(), *d_NT = res.NT.as<uint64_t>(), *d_dNT = dNT.as<uint64_t>();
+    uint64_t *Dbuf[2] = {D0.as<uint64_t>(), D1.as<uint64_t>()};
+    uint64_t *act[3] = {acts.as<uint64_t>(), acts.as<uint64_t>() + aw, acts.as<uint64_t>() + 2 * aw};
+    unsigned long long *d_ctr = ctr.as<unsigned long long>();
+
+    // events: [0] start, [1] end; profiling pool after that
+    std::vector<hipEvent_t> ev;
+    struct EvGuard {
+        std::vector<hipEvent_t> *v;
+        ~EvGuard() {
+            for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+        }
+    } evg{&ev};
+    auto event = [&](size_t i) -> hipEvent_t {
+        while (ev.size() <= i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            ev.push_back(e);
+        }
+        return ev[i];
+    };
+    if (!event(1)) return fail(CFPQ_ERR_DEVICE, "hipEventCreate failed");
+    const bool prof = o.profile != 0;
+    res.profiled = prof;
+    // launch timing: event before each launch of a chunk plus one after it
+    auto prof_mark = [&](uint32_t j) -> cfpq_status {
+        if (!prof) return CFPQ_OK;
+        hipEvent_t e = event(2 + j);
+        if (!e) return fail(CFPQ_ERR_DEVICE, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e, s));
+        return CFPQ_OK;
+    };
+    auto prof_ms = [&](uint32_t j) -> double {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2 + j], ev[3 + j]) != hipSuccess) return 0.0;
+        return ms;
+    };
+
+    HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_fill(d_T, qw, 0, s));
+    HIP_TRY(launch_fill(d_NT, bw, 0, s));
+    HIP_TRY(launch_fill(d_dNT, bw, 0, s));
+    HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
+    HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), (uint64_t)nB * Pn, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)d_ctr, ring_words, 0, s));
+    HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, s));
+    HIP_TRY(launch_eps(d_NT, d_dNT, dnt_act.as<uint64_t>(), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
+                       Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+
+    std::vector<uint64_t> box_delta(nB, 0);
+    for (uint32_t b : p.eps_boxes) box_delta[b] = n;
+
+    PinnedCounters pc;
+    if (!pc.ensure(4096 * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+    uint32_t slot = 0;
+    // every slot a launch may use must read zero before the launch; the ring
+    // is cleared whole when it would wrap (only at points where the previous
+    // launch is known to have run, see below)
+    auto need_slots = [&](uint32_t k) -> cfpq_status {
+        if (slot + k >= kRingSlots) {
+            HIP_TRY(launch_fill((uint64_t *)d_ctr, ring_words, 0, s));
+            slot = 0;
+        }
+        return CFPQ_OK;
+    };
+    auto fetch = [&](uint32_t first, uint32_t k) -> cfpq_status {
+        if (!pc.ensure((size_t)k * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+        HIP_TRY(hipMemcpyAsync(pc.h, d_ctr + (uint64_t)first * kSlotWords, (size_t)k * kSlotWords * 8,
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return CFPQ_OK;
+    };
+
+    const uint32_t grid = gather_grid((uint64_t)nQ * n);
+    uint32_t levels_hint = 16;
+    uint32_t it = 0;
+    res.deltas.clear();
+    for (;;) {
+        ++it;
+        if (o.max_iters && it > o.max_iters)
+            return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+        bool can_seed = (it == 1);
+        for (uint32_t b = 0; b < nB; ++b) can_seed |= (box_delta[b] && p.box_used[b]);
+        if (!can_seed) {
+            res.deltas.push_back(0);
+            break;
+        }
+        for (uint32_t gi = 0; gi < groups; ++gi) {
+            const uint32_t w0 = gi * G, gw = std::min(G, Pn - w0);
+            HIP_TRY(launch_fill(act[0], 3 * aw, 0, s));
+            GatherArgs a{};
+            a.n = n; a.P = P; a.Pn = Pn; a.n_terms = p.n_terms; a.nQ = nQ;
+            a.w0 = w0; a.gw = gw; a.G = G;
+            a.goff = g.off.as<uint32_t>(); a.gidx = g.idx.as<uint32_t>();
+            a.in_off = tb.in_off; a.in_tr = tb.in_tr;
+            a.T = d_T; a.tnz = tnz.as<uint64_t>(); a.ctr = d_ctr; a.clear_words = (uint32_t)aw;
+            // Kronecker product of the RSM with the new edges (seed); the seed
+            // and the first chunk of levels always fit before a ring clear
+            if ((st = need_slots(levels_hint + 2)) != CFPQ_OK) return st;
+            a.sel = d_dNT; a.sel_act = dnt_act.as<uint64_t>();
+            a.src = d_T; a.src_pitch = P; a.src_off = w0; a.src_act = tnz.as<uint64_t>();
+            a.dn = Dbuf[0]; a.actn = act[0]; a.act_clear = nullptr;
+            a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1);
+            const uint32_t seed_slot = slot;
+            if ((st = prof_mark(0)) != CFPQ_OK) return st;
+            HIP_TRY(launch_gather(a, true, grid, s));
+            if ((st = prof_mark(1)) != CFPQ_OK) return st;
+            if (prof) {
+                if ((st = fetch(seed_slot, 1)) != CFPQ_OK) return st;
+                res.prof[CFPQ_KERNEL_SEED].launches++;
+                res.prof[CFPQ_KERNEL_SEED].ms += prof_ms(0);
+            }
+            uint32_t prev = slot++;
+            uint64_t rows_in = prof ? pc.h[2] : 0;   // frontier rows feeding the next level
+            // incremental closure: frontier levels until one adds nothing
+            uint32_t li = 1;
+            for (;;) {
+                const uint32_t li0 = li;
+                const uint32_t k = levels_hint;
+                if ((st = need_slots(k + 1)) != CFPQ_OK) return st;
+                const uint32_t first_slot = slot;
+                // after a ring clear the previous count is gone; the previous
+                // launch is known to have run (its count was read as nonzero,
+                // or it is the seed), so the next one runs unconditionally
+                if (first_slot == 0 && prev != 0) prev = kNoSlot;
+                for (uint32_t j = 0; j < k; ++j, ++li) {
+                    a.sel = d_NT; a.sel_act = nullptr;
+                    a.src = Dbuf[(li - 1) & 1]; a.src_pitch = G; a.src_off = 0;
+                    a.src_act = act[(li - 1) % 3];
+                    a.dn = Dbuf[li & 1]; a.actn = act[li % 3]; a.act_clear = act[(li + 1) % 3];
+                    a.slot_prev = prev; a.slot_cur = slot; a.seed_terms = 0;
+                    if ((st = prof_mark(j)) != CFPQ_OK) return st;
+                    HIP_TRY(launch_gather(a, false, grid, s));
+                    prev = slot++;
+                }
+                if ((st = prof_mark(k)) != CFPQ_OK) return st;
+                if ((st = fetch(first_slot, k)) != CFPQ_OK) return st;
+                uint32_t used = k;
+                for (uint32_t j = 0; j < k; ++j)
+                    if (pc.h[(size_t)j * kSlotWords] == 0) {
+                        used = j;
+                        break;
+                    }
+                if (prof) {
+                    auto &pl = res.prof[CFPQ_KERNEL_LEVEL];
+                    for (uint32_t j = 0; j < k; ++j) {
+                        pl.launches++;
+                        pl.ms += prof_ms(j);
+                        const uint64_t fed = pc.h[(size_t)j * kSlotWords + 1];
+                        const uint64_t gained = pc.h[(size_t)j * kSlotWords + 2];
+                        if (j <= used) pl.bytes += 8ull * gw * (rows_in + 3 * fed);
+                        rows_in = gained;
+                    }
+                }
+                if (used < k) {
+                    // levels this tile needed; the next tile of the same graph
+                    // needs about as many
+                    levels_hint = std::max<uint32_t>(4, (li0 - 1) + used + 2);
+                    break;
+                }
+                levels_hint = std::min<uint32_t>(levels_hint * 2, 1024);
+            }
+        }
+        // write-back
+        if ((st = need_slots(nB + 1)) != CFPQ_OK) return st;
+        HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), (uint64_t)nB * Pn, 0, s));
+        WritebackArgs w{};
+        w.n = n; w.P = P; w.Pn = Pn; w.nB = nB; w.fin_off = tb.fin_off; w.fin = tb.fin;
+        w.T = d_T; w.NT = d_NT; w.dNT = d_dNT; w.dnt_act = dnt_act.as<uint64_t>();
+        w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
+        w.iter = it; w.ctr = d_ctr; w.slot_base = slot;
+        if ((st = prof_mark(0)) != CFPQ_OK) return st;
+        HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
+        if ((st = prof_mark(1)) != CFPQ_OK) return st;
+        if ((st = fetch(slot, nB)) != CFPQ_OK) return st;
+        if (prof) {
+            auto &pw = res.prof[CFPQ_KERNEL_WRITEBACK];
+            pw.launches++;
+            pw.ms += prof_ms(0);
+            for (uint32_t b = 0; b < nB; ++b)
+                pw.bytes += 8ull * Pn * n * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + (p.fin_off[b + 1] > p.fin_off[b] ? 3 : 0));
+        }
+        slot += nB;
+        uint64_t delta = 0;
+        for (uint32_t b = 0; b < nB; ++b) {
+            box_delta[b] = pc.h[(size_t)b * kSlotWords];
+            delta += box_delta[b];
+        }
+        res.deltas.push_back(delta);
+        if (delta == 0) break;
+    }
+    HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(hipEventSynchronize(ev[1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    res.ms = ms;
+    res.iterations = it;
+    if (o.keep_blocks) res.T = std::move(T);
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FUSED strategy: a workgroup per query, many queries per launch
+// ---------------------------------------------------------------------------
+struct FusedJob {
+    Plan plan;
+    Tables tb;
+    DevBuf work, T;
+    FusedQuery q{};
+    cfpq_result_s *res = nullptr;
+    bool keep_blocks = false;
+};
+
+bool fused_ok(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
+    return g.n <= kFusedMaxN && r.n_boxes <= kFusedMaxBoxesHost;
+}
+
+cfpq_status prepare_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o,
+                          cfpq_result_s &res, FusedJob &job) {
+    hipStream_t s = (hipStream_t)o.stream;
+    const Alloc *al = &res.alloc;
+    job.plan = make_plan(g, r);
+    cfpq_status st = upload_tables(job.plan, al, s, job.tb);
+    if (st != CFPQ_OK) return st;
+    const Plan &p = job.plan;
+    const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
+    const uint64_t aw = (uint64_t)p.nQ * p.Pn, bb = (uint64_t)p.nB * p.Pn;
+    const uint64_t words = 2 * qw /*D, Dn*/ + bw /*dNT*/ + 3 * aw + bb + 2 + kStatsCap;
+    if (!job.T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !job.work.alloc(al, words * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (fused query)");
+    if (o.keep_rank) {
+        if (!res.rank.alloc(al, (uint64_t)p.nB * p.n * p.n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
+        HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)p.nB * p.n * p.n, s));
+    }
+    uint64_t *w = job.work.as<uint64_t>();
+    FusedQuery &q = job.q;
+    q.n = p.n; q.P = p.P; q.Pn = p.Pn; q.n_terms = p.n_terms; q.nQ = p.nQ; q.nB = p.nB;
+    q.goff = g.off.as<uint32_t>(); q.gidx = g.idx.as<uint32_t>();
+    q.in_off = job.tb.in_off; q.in_tr = job.tb.in_tr; q.starts = job.tb.starts;
+    q.fin_off = job.tb.fin_off; q.fin = job.tb.fin; q.nullable = job.tb.nullable; q.box_used = job.tb.box_used;
+    q.T = job.T.as<uint64_t>(); q.NT = res.NT.as<uint64_t>();
+    q.D = w; w += qw;
+    q.Dn = w; w += qw;
+    q.dNT = w; w += bw;
+    q.act = w; w += aw;
+    q.actn = w; w += aw;
+    q.tnz = w; w += aw;
+    q.dnt_act = w; w += bb;
+    q.stats = (unsigned long long *)w;
+    q.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
+    q.max_iters = o.max_iters;
+    q.stats_cap = kStatsCap;
+    job.res = &res;
+    job.keep_blocks = o.keep_blocks;
+    return CFPQ_OK;
+}
+
+cfpq_status run_fused_jobs(std::vector<FusedJob> &jobs, const cfpq_query_opts &o, const Alloc *al) {
+    if (jobs.empty()) return CFPQ_OK;
+    hipStream_t s = (hipStream_t)o.stream;
+    std::vector<FusedQuery> qs;
+    for (auto &j : jobs) qs.push_back(j.q);
+    DevBuf dq;
+    if (!dq.alloc(al, qs.size() * sizeof(FusedQuery) + 64, s)) return fail(CFPQ_ERR_OOM, "device allocation failed");
+    uint8_t *base = dq.as<uint8_t>();
+    uint32_t *next = (uint32_t *)(base + qs.size() * sizeof(FusedQuery));
+    HIP_TRY(hipMemcpyAsync(base, qs.data(), qs.size() * sizeof(FusedQuery), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(next, 0, 4, s));
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } evg{ev0, ev1};
+    HIP_TRY(hipEventRecord(ev0, s));
+    HIP_TRY(launch_fused((const FusedQuery *)base, (uint32_t)qs.size(), next, s));
+    HIP_TRY(hipEventRecord(ev1, s));
+    HIP_TRY(hipEventSynchronize(ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    std::vector<unsigned long long> stats(2 + kStatsCap);
+    for (auto &j : jobs) {
+        HIP_TRY(hipMemcpy(stats.data(), j.q.stats, stats.size() * 8, hipMemcpyDeviceToHost));
+        if (stats[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+        j.res->iterations = (uint32_t)stats[0];
+        j.res->deltas.assign(stats.begin() + 2, stats.begin() + 2 + std::min<uint64_t>(stats[0], kStatsCap));
+        j.res->ms = ms;  // the launch's time, shared by the batch
+        if (j.keep_blocks) j.res->T = std::move(j.T);
+    }
+    return CFPQ_OK;
+}
+
+cfpq_result_s *new_result(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
+    cfpq_result_s *res = new (std::nothrow) cfpq_result_s;
+    if (!res) return nullptr;
+    res->device = g.device;
+    res->n = g.n;
+    res->Pn = (g.n + 63) / 64;
+    res->P = round_up(res->Pn, 8);
+    res->nB = r.n_boxes;
+    res->nQ = r.n_states;
+    res->stream = (hipStream_t)o.stream;
+    res->alloc = Alloc(o.alloc);
+    res->rsm = r;
+    res->n_labels = g.n_labels;
+    if (o.keep_rank) {
+        res->out_off = g.h_out_off;
+        res->out = g.h_out;
+    }
+    return res;
+}
+
+cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
+    if (o.strategy > CFPQ_STRATEGY_FUSED) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.keep_rank && g.n > 16384) return fail(CFPQ_ERR_LIMIT, "keep_rank needs n <= 16384");
+    if (o.strategy == CFPQ_STRATEGY_FUSED && !fused_ok(g, r))
+        return fail(CFPQ_ERR_LIMIT, "fused strategy needs n <= 2048 and at most 64 boxes");
+    return CFPQ_OK;
+}
+
+bool use_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
+    if (o.strategy == CFPQ_STRATEGY_FUSED) return true;
+    if (o.strategy == CFPQ_STRATEGY_LEVELS) return false;
+    return fused_ok(g, r) && g.n <= 1024;
+}
+
+}  // namespace
+
+extern "C" cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opts *opts, cfpq_result *out) {
+    if (!out) return fail(CFPQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    cfpq_status st = check_pair(g, r);
+    if (st != CFPQ_OK) return st;
+    cfpq_query_opts o{};
+    if (opts) o = *opts;
+    if ((st = check_opts(*g, *r, o)) != CFPQ_OK) return st;
+    std::unique_ptr<cfpq_result_s> res(new_result(*g, *r, o));
+    if (!res) return fail(CFPQ_ERR_OOM, "host allocation failed");
+    try {
+        if (use_fused(*g, *r, o)) {
+            std::vector<FusedJob> jobs(1);
+            if ((st = prepare_fused(*g, *r, o, *res, jobs[0])) != CFPQ_OK) return st;
+            if ((st = run_fused_jobs(jobs, o, &res->alloc)) != CFPQ_OK) return st;
+        } else {
+            if ((st = run_levels(*g, *r, o, *res)) != CFPQ_OK) return st;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    *out = res.release();
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm *rsms, uint32_t k,
+                                        const cfpq_query_opts *opts, cfpq_result *results) {
+    if (!results || (k && (!graphs || !rsms))) return fail(CFPQ_ERR_INVALID, "NULL array");
+    for (uint32_t i = 0; i < k; ++i) results[i] = nullptr;
+    cfpq_query_opts o{};
+    if (opts) o = *opts;
+    std::vector<std::unique_ptr<cfpq_result_s>> res(k);
+    cfpq_status st = CFPQ_OK;
+    try {
+        std::vector<FusedJob> jobs;
+        std::vector<uint32_t> big;
+        for (uint32_t i = 0; i < k; ++i) {
+            if ((st = check_pair(graphs[i], rsms[i])) != CFPQ_OK) return st;
+            if ((st = check_opts(*graphs[i], *rsms[i], o)) != CFPQ_OK) return st;
+            res[i].reset(new_result(*graphs[i], *rsms[i], o));
+            if (!res[i]) return fail(CFPQ_ERR_OOM, "host allocation failed");
+            if (use_fused(*graphs[i], *rsms[i], o)) {
+                jobs.emplace_back();
+                if ((st = prepare_fused(*graphs[i], *rsms[i], o, *res[i], jobs.back())) != CFPQ_OK) return st;
+            } else {
+                big.push_back(i);
+            }
+        }
+        if ((st = run_fused_jobs(jobs, o, &res[0]->alloc)) != CFPQ_OK) return st;
+        jobs.clear();
+        for (uint32_t i : big)
+            if ((st = run_levels(*graphs[i], *rsms[i], o, *res[i])) != CFPQ_OK) return st;
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    for (uint32_t i = 0; i < k; ++i) results[i] = res[i].release();
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// result accessors
+// ---------------------------------------------------------------------------
+namespace {
+
+cfpq_status check_box(cfpq_result r, uint32_t box) {
+    if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
+    if (box >= r->nB) return fail(CFPQ_ERR_INVALID, "box out of range");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != r->device) return fail(CFPQ_ERR_INVALID, "result lives on another device");
+    return CFPQ_OK;
+}
+
+cfpq_status scratch_u64(cfpq_result r, unsigned long long **p) {
+    if (!r->scratch.p && !r->scratch.alloc(&r->alloc, 64, r->stream))
+        return fail(CFPQ_ERR_OOM, "device allocation failed");
+    *p = r->scratch.as<unsigned long long>();
+    return CFPQ_OK;
+}
+
+// transposed rows [n][P] -> row-major bitmap [n][Pn] at dst (device)
+cfpq_status to_rowmajor(cfpq_result r, const uint64_t *src, uint64_t *dst_dev) {
+    HIP_TRY(launch_transpose(src, r->P, dst_dev, r->Pn, r->n, r->stream));
+    return CFPQ_OK;
+}
+
+cfpq_status fetch_bitmap(cfpq_result r, const uint64_t *src, uint64_t *dst, uint64_t dst_words,
+                         int on_device) {
+    const uint64_t need = (uint64_t)r->n * r->Pn;
+    if (!dst) return fail(CFPQ_ERR_INVALID, "dst is NULL");
+    if (dst_words < need) return fail(CFPQ_ERR_BUFFER, "bitmap buffer too small: need " + std::to_string(need) + " words");
+    if (on_device) {
+        cfpq_status st = to_rowmajor(r, src, dst);
+        if (st != CFPQ_OK) return st;
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        return CFPQ_OK;
+    }
+    DevBuf tmp;
+    if (!tmp.alloc(&r->alloc, need * 8, r->stream)) return fail(CFPQ_ERR_OOM, "device allocation failed");
+    cfpq_status st = to_rowmajor(r, src, tmp.as<uint64_t>());
+    if (st != CFPQ_OK) return st;
+    HIP_TRY(hipMemcpyAsync(dst, tmp.p, need * 8, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return CFPQ_OK;
+}
+
+const uint64_t *box_rows(cfpq_result r, uint32_t box) {
+    return r->NT.as<uint64_t>() + (uint64_t)box * r->n * r->P;
+}
+
+}  // namespace
+
+extern "C" cfpq_status cfpq_result_count(cfpq_result r, uint32_t box, uint64_t *pairs) {
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    if (!pairs) return fail(CFPQ_ERR_INVALID, "pairs is NULL");
+    unsigned long long *d = nullptr;
+    if ((st = scratch_u64(r, &d)) != CFPQ_OK) return st;
+    HIP_TRY(hipMemsetAsync(d, 0, 8, r->stream));
+    HIP_TRY(launch_popcount(box_rows(r, box), r->n, r->P, r->Pn, d, r->stream));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    *pairs = h;
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_result_hash(cfpq_result r, uint32_t box, uint64_t *hash) {
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    if (!hash) return fail(CFPQ_ERR_INVALID, "hash is NULL");
+    unsigned long long *d = nullptr;
+    if ((st = scratch_u64(r, &d)) != CFPQ_OK) return st;
+    HIP_TRY(hipMemsetAsync(d, 0, 8, r->stream));
+    HIP_TRY(launch_hash(box_rows(r, box), r->n, r->P, d, r->stream));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, d, 8, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    *hash = h;
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_result_bitmap(cfpq_result r, uint32_t box, uint64_t *dst, uint64_t dst_words,
+                                          int dst_on_device) {
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    return fetch_bitmap(r, box_rows(r, box), dst, dst_words, dst_on_device);
+}
+
+extern "C" cfpq_status cfpq_result_pairs(cfpq_result r, uint32_t box, uint32_t *uv, uint64_t cap_pairs,
+                                         uint64_t *n_pairs) {
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    if (!n_pairs) return fail(CFPQ_ERR_INVALID, "n_pairs is NULL");
+    uint64_t cnt = 0;
+    if ((st = cfpq_result_count(r, box, &cnt)) != CFPQ_OK) return st;
+    *n_pairs = cnt;
+    if (cap_pairs < cnt) return fail(CFPQ_ERR_BUFFER, "pairs buffer too small: need " + std::to_string(cnt));
+    if (cnt && !uv) return fail(CFPQ_ERR_INVALID, "uv is NULL");
+    std::vector<uint64_t> bm;
+    try {
+        bm.resize((uint64_t)r->n * r->Pn);
+    } catch (...) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    if ((st = fetch_bitmap(r, box_rows(r, box), bm.data(), bm.size(), 0)) != CFPQ_OK) return st;
+    uint64_t k = 0;
+    for (uint32_t u = 0; u < r->n; ++u)
+        for (uint32_t w = 0; w < r->Pn; ++w) {
+            uint64_t bits = bm[(uint64_t)u * r->Pn + w];
+            while (bits) {
+                const int b = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                uv[2 * k] = u;
+                uv[2 * k + 1] = w * 64 + b;
+                ++k;
+            }
+        }
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_result_block(cfpq_result r, uint32_t q_start, uint32_t q_final, uint64_t *dst,
+                                         uint64_t dst_words) {
+    if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
+    if (!r->T.p) return fail(CFPQ_ERR_INVALID, "closure blocks were not kept (keep_blocks)");
+    if (q_start >= r->nQ || q_final >= r->nQ) return fail(CFPQ_ERR_INVALID, "state out of range");
+    const uint32_t b = r->rsm.state_box[q_final];
+    if (r->rsm.box_start[b] != q_start)
+        return fail(CFPQ_ERR_INVALID, "q_start is not the initial state of q_final's box");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != r->device) return fail(CFPQ_ERR_INVALID, "result lives on another device");
+    return fetch_bitmap(r, r->T.as<uint64_t>() + (uint64_t)q_final * r->n * r->P, dst, dst_words, 0);
+}
+
+extern "C" cfpq_status cfpq_result_stats(cfpq_result r, uint32_t *iterations, uint64_t *delta, uint32_t cap,
+                                         double *fixpoint_ms) {
+    if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
+    if (iterations) *iterations = r->iterations;
+    if (delta)
+        for (uint32_t i = 0; i < cap && i < r->deltas.size(); ++i) delta[i] = r->deltas[i];
+    if (fixpoint_ms) *fixpoint_ms = r->ms;
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_result_profile(cfpq_result r, uint32_t kind, uint64_t *launches, double *ms,
+                                           uint64_t *bytes) {
+    if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
+    if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile, levels strategy)");
+    if (kind > CFPQ_KERNEL_WRITEBACK) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
+    if (launches) *launches = r->prof[kind].launches;
+    if (ms) *ms = r->prof[kind].ms;
+    if (bytes) *bytes = r->prof[kind].bytes;
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single witness (Sec. 3.2)
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Witness {
+    cfpq_result r;
+    std::vector<uint32_t> *out;
+    uint64_t limit;
+    bool overflow = false;
+
+    uint8_t rank(uint32_t N, uint32_t u, uint32_t v) const {
+        return r->h_rank[((uint64_t)N * r->n + u) * r->n + v];
+    }
+
+    // product-graph BFS inside box N from (start, u) to (final, v) using
+    // terminal edges and nonterminal edges of rank < rk; expands the path.
+    bool expand(uint32_t N, uint32_t u, uint32_t v, uint8_t rk) {
+        if (overflow) return false;
+        if (rk == 0) return u == v;  // the epsilon loop: empty path
+        const cfpq_rsm_s &R = r->rsm;
+        const uint32_t n = r->n, nQ = R.n_states;
+        const uint32_t start = R.box_start[N];
+        std::vector<uint32_t> states;
+        for (uint32_t q = 0; q < nQ; ++q)
+            if (R.state_box[q] == N) states.push_back(q);
+        // parent pointers over product nodes id = q * n + x
+        std::vector<int64_t> par((uint64_t)nQ * n, -1);
+        std::vector<uint32_t> par_sym((uint64_t)nQ * n, 0);
+        std::vector<uint32_t> queue;
+        const uint64_t s0 = (uint64_t)start * n + u;
+        par[s0] = (int64_t)s0;
+        queue.push_back((uint32_t)s0);
+        int64_t hit = -1;
+        for (size_t h = 0; h < queue.size() && hit < 0; ++h) {
+            const uint32_t node = queue[h];
+            const uint32_t q = node / n, x = node % n;
+            for (size_t t = 0; t < R.t_src.size() && hit < 0; ++t) {
+                if (R.t_src[t] != q) continue;
+                const uint32_t f = R.t_dst[t], sym = R.t_sym[t];
+                auto visit = [&](uint32_t y) {
+                    const uint64_t id = (uint64_t)f * n + y;
+                    if (par[id] >= 0) return;
+                    par[id] = node;
+                    par_sym[id] = sym;
+                    queue.push_back((uint32_t)id);
+                    if (y == v && R.is_final[f]) hit = (int64_t)id;
+                };
+                if (sym < R.n_terms) {
+                    const uint64_t a = r->out_off[(uint64_t)sym * (n + 1) + x], b = r->out_off[(uint64_t)sym * (n + 1) + x + 1];
+                    for (uint64_t e = a; e < b && hit < 0; ++e) visit(r->out[e]);
+                } else {
+                    const uint32_t M = sym - R.n_terms;
+                    for (uint32_t y = 0; y < n && hit < 0; ++y)
+                        if (rank(M, x, y) < rk) visit(y);
+                }
+            }
+        }
+        if (hit < 0) return false;
+        // walk back
+        std::vector<std::array<uint32_t, 3>> steps;  // (x, sym, y)
+        for (uint64_t id = (uint64_t)hit; id != s0;) {
+            const uint64_t pid = (uint64_t)par[id];
+            steps.push_back({(uint32_t)(pid % n), par_sym[id], (uint32_t)(id % n)});
+            id = pid;
+        }
+        std::reverse(steps.begin(), steps.end());
+        for (auto &st : steps) {
+            if (st[1] < R.n_terms) {
+                if (out->size() / 3 >= limit) {
+                    overflow = true;
+                    return false;
+                }
+                out->push_back(st[0]);
+                out->push_back(st[1]);
+                out->push_back(st[2]);
+            } else {
+                const uint32_t M = st[1] - R.n_terms;
+                if (!expand(M, st[0], st[2], rank(M, st[0], st[2]))) return false;
+            }
+        }
+        return true;
+    }
+};
+
+}  // namespace
+
+extern "C" cfpq_status cfpq_extract_path(cfpq_result r, uint32_t box, uint32_t u, uint32_t v, uint32_t *edges,
+                                         uint64_t cap_edges, uint64_t *n_edges) {
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    if (!n_edges) return fail(CFPQ_ERR_INVALID, "n_edges is NULL");
+    if (!r->rank.p) return fail(CFPQ_ERR_INVALID, "ranks were not kept (keep_rank)");
+    if (u >= r->n || v >= r->n) return fail(CFPQ_ERR_INVALID, "vertex out of range");
+    if (r->iterations > 254) return fail(CFPQ_ERR_LIMIT, "more than 254 iterations: ranks saturated");
+    if (r->h_rank.empty()) {
+        const uint64_t n = r->n;
+        std::vector<uint8_t> t;
+        try {
+            t.resize((uint64_t)r->nB * n * n);
+            r->h_rank.resize(t.size());
+        } catch (...) {
+            return fail(CFPQ_ERR_OOM, "host allocation failed");
+        }
+        HIP_TRY(hipMemcpy(t.data(), r->rank.p, t.size(), hipMemcpyDeviceToHost));
+        // device layout [N][v][u] -> host [N][u][v]
+        for (uint64_t N = 0; N < r->nB; ++N)
+            for (uint64_t vv = 0; vv < n; ++vv)
+                for (uint64_t uu = 0; uu < n; ++uu) r->h_rank[(N * n + uu) * n + vv] = t[(N * n + vv) * n + uu];
+    }
+    const uint8_t rk = r->h_rank[((uint64_t)box * r->n + u) * r->n + v];
+    if (rk == 0xFF) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
+    std::vector<uint32_t> out;
+    Witness w{r, &out, (uint64_t)1 << 26};
+    if (!w.expand(box, u, v, rk)) {
+        if (w.overflow) return fail(CFPQ_ERR_LIMIT, "witness longer than 2^26 edges");
+        return fail(CFPQ_ERR_DEVICE, "internal error: no witness through lower-rank edges");
+    }
+    *n_edges = out.size() / 3;
+    if (cap_edges < out.size() / 3) return fail(CFPQ_ERR_BUFFER, "edge buffer too small");
+    if (!out.empty()) {
+        if (!edges) return fail(CFPQ_ERR_INVALID, "edges is NULL");
+        std::memcpy(edges, out.data(), out.size() * 4);
+    }
+    return CFPQ_OK;
+}
+
+extern "C" void cfpq_result_destroy(cfpq_result r) { delete r; }
+
+extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.1"; }

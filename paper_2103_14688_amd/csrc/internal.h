@@ -1,0 +1,115 @@
+// Library-internal declarations shared by the host driver (api.hip) and the
+// device kernels (kernels.hip).  Not part of the C ABI.
+//
+// Data layout on the device (HBM), for a query over a graph with n vertices
+// and an RSM with nQ states and nB boxes:
+//
+//   The closure is kept "by columns of sources".  Row (q, v) of the state
+//   array T is a bitset over source vertices u: bit u set iff the product
+//   node (box_start(q), u) reaches (q, v) -- i.e. the box-start rows of the
+//   closure C3 of Listing 1, transposed.  Box-start states also hold the
+//   trivial bit u == v.  Words per row: P (padded), of which Pn = ceil(n/64)
+//   carry vertices.
+//
+//     T   [nQ][n][P]   closure rows (monotone)
+//     NT  [nB][n][P]   nonterminal matrices M2^N, transposed: row v = {u}
+//     dNT [nB][n][P]   edges NT gained in the last write-back (A2 of Listing 1)
+//     D,Dn[nQ][n][G]   frontier of the current closure level, restricted to
+//                      one source tile of G words (bits over sources)
+//     act[nQ][Pn]      bitset of frontier rows that are non-empty
+//     tnz[nQ][Pn]      bitset of T rows that are non-empty
+//
+//   Graph label matrices are stored by columns: for vertex v and label l the
+//   sorted predecessors gidx[goff[l*(n+1)+v] .. goff[l*(n+1)+v+1]).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cfpq {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+constexpr uint32_t kRingSlots = 1u << 16;   // device counter ring
+constexpr uint32_t kSlotWords = 4;          // per slot: new bits, rows fed, rows gaining bits
+
+struct InTrans {
+    uint32_t src;   // source state
+    uint32_t sym;   // < n_terms: graph label; else n_terms + box
+};
+
+// One closure launch: seeding from new edges (Kronecker product of the RSM
+// with A2) or one frontier level of the incremental closure.
+struct GatherArgs {
+    uint32_t n, P, Pn, n_terms, nQ;
+    uint32_t w0, gw, G;           // source tile [w0, w0+gw), frontier pitch G
+    const uint32_t *goff, *gidx;
+    const uint32_t *in_off;       // [nQ+1] incoming transitions per target state
+    const InTrans *in_tr;
+    uint64_t *T;
+    const uint64_t *sel;          // nonterminal selectors: seed -> dNT, level -> NT
+    const uint64_t *sel_act;      // seed: dnt_act bitset [nB][Pn]; level: null
+    const uint64_t *src;          // rows OR-ed in: seed -> T, level -> D
+    uint32_t src_pitch, src_off;
+    const uint64_t *src_act;      // seed: tnz; level: act
+    uint64_t *dn;                 // next frontier [nQ][n][G]
+    uint64_t *actn;               // next frontier row bitset (pre-cleared)
+    uint64_t *act_clear;          // bitset to clear for the launch after next (or null)
+    uint32_t clear_words;
+    uint64_t *tnz;
+    unsigned long long *ctr;      // counter ring, kSlotWords per slot
+    uint32_t slot_prev;           // kNoSlot: run unconditionally
+    uint32_t slot_cur;            // counts of this launch
+    uint32_t seed_terms;          // seed launch: terminal transitions take part
+};
+
+struct WritebackArgs {
+    uint32_t n, P, Pn, nB;
+    const uint32_t *fin_off, *fin; // final states per box
+    const uint64_t *T;
+    uint64_t *NT, *dNT, *dnt_act;  // dnt_act pre-cleared
+    uint8_t *rank;                 // optional [nB][n][n]: rank[N][v][u]
+    uint32_t iter;
+    unsigned long long *ctr;
+    uint32_t slot_base;            // new edges of box N counted at slot_base + N
+};
+
+// kernels.hip
+hipError_t launch_fill(uint64_t *p, uint64_t words, uint64_t value, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint64_t bytes, hipStream_t s);
+hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
+                            const uint32_t *states, uint32_t n_states, hipStream_t s);
+hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
+                      uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb, hipStream_t s);
+hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s);
+hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s);
+hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
+                           unsigned long long *out, hipStream_t s);
+hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned long long *out,
+                       hipStream_t s);
+// dst[u][v-word] (row-major, pitch dst_pitch) from src[v][u-word] (pitch src_pitch)
+hipError_t launch_transpose(const uint64_t *src, uint32_t src_pitch, uint64_t *dst,
+                            uint32_t dst_pitch, uint32_t n, hipStream_t s);
+
+// Fused small-graph fixpoint: one workgroup runs a whole query.
+struct FusedQuery {
+    uint32_t n, P, Pn, n_terms, nQ, nB;
+    const uint32_t *goff, *gidx;
+    const uint32_t *in_off;
+    const InTrans *in_tr;
+    const uint32_t *starts;        // [nB] box start states
+    const uint32_t *fin_off, *fin;
+    const uint8_t *nullable;       // [nB]
+    const uint8_t *box_used;       // [nB] box labels some transition
+    uint64_t *T, *NT, *dNT, *D, *Dn;   // D/Dn: [nQ][n][P]
+    uint64_t *act, *actn, *tnz, *dnt_act;
+    uint8_t *rank;
+    unsigned long long *stats;     // [0] iterations, [1] status, [2..] per-iteration deltas
+    uint32_t max_iters, stats_cap;
+};
+hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query,
+                        hipStream_t s);
+
+}  // namespace cfpq

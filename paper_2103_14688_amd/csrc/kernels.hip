@@ -1,0 +1,599 @@
+// Device kernels of the Kronecker-product fixpoint (Sec. 3.1, Listing 1) for
+// gfx950.  Layout and buffer roles are described in internal.h.
+//
+// The Kronecker product M1 (x) M2 is never materialised (Sec. 2.4: block
+// (s, f) of the product is the OR of M2^x over the transitions (s, x, f)).
+// A closure launch therefore walks, for every target product row (f, v),
+// the incoming transitions (s, x, f) of state f and the predecessors y of v
+// under x, and ORs the source bitsets of rows (s, y).  Because a row is a
+// bitset over source vertices, one 64-bit word carries 64 closure rows of
+// the paper's C3 at once, and a wavefront handles 64 consecutive words of a
+// row with one coalesced 512-byte load per predecessor.
+#include "internal.h"
+
+namespace cfpq {
+
+constexpr int kChunks = 8;   // 64-word chunks per pass over a source tile
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+    return x;
+}
+
+__device__ __forceinline__ bool test_bit(const uint64_t *bits, uint32_t i) {
+    return (bits[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood 2014): the generator's first
+// output for seed x.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// simple fills / setup
+// ---------------------------------------------------------------------------
+__global__ void k_fill(uint64_t *p, uint64_t words, uint64_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+__global__ void k_fill_u8(uint8_t *p, uint64_t bytes) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+static uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 8192) {
+    uint64_t g = (items + block - 1) / block;
+    if (g == 0) g = 1;
+    if (g > cap) g = cap;
+    return (uint32_t)g;
+}
+
+hipError_t launch_fill(uint64_t *p, uint64_t words, uint64_t value, hipStream_t s) {
+    if (!words) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(words)), dim3(kBlock), 0, s, p, words, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint64_t bytes, hipStream_t s) {
+    if (!bytes) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(bytes)), dim3(kBlock), 0, s, p, bytes);
+    return hipGetLastError();
+}
+
+// Box-start rows hold the trivial source bit: (q_N^0, v) is where the search
+// from source v starts.  T rows of states[i] get bit v in row v.
+__device__ void seed_diag_body(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
+                               const uint32_t *states, uint32_t n_states, uint64_t tid,
+                               uint64_t nthreads) {
+    for (uint64_t i = tid; i < (uint64_t)n_states * n; i += nthreads) {
+        uint32_t s = states[i / n], v = (uint32_t)(i % n);
+        T[((uint64_t)s * n + v) * P + (v >> 6)] |= 1ull << (v & 63);
+    }
+    for (uint64_t i = tid; i < (uint64_t)n_states * Pn; i += nthreads) {
+        uint32_t s = states[i / Pn], k = (uint32_t)(i % Pn);
+        uint32_t hi = n - k * 64;
+        tnz[(uint64_t)s * Pn + k] = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+    }
+}
+
+__global__ void k_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
+                            const uint32_t *states, uint32_t n_states) {
+    seed_diag_body(T, tnz, n, P, Pn, states, n_states,
+                   (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                   (uint64_t)gridDim.x * blockDim.x);
+}
+
+hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
+                            const uint32_t *states, uint32_t n_states, hipStream_t s) {
+    if (!n_states) return hipSuccess;
+    hipLaunchKernelGGL(k_seed_diag, dim3(grid_for((uint64_t)n_states * n)), dim3(kBlock), 0, s, T,
+                       tnz, n, P, Pn, states, n_states);
+    return hipGetLastError();
+}
+
+// Epsilon initialisation (Listing 1, before the loop): a box whose initial
+// state is final derives the empty word, so M2^N gets every loop (v, v); the
+// loops are also this iteration's new edges A2^N.
+__device__ void eps_body(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank,
+                         uint32_t n, uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb,
+                         uint64_t tid, uint64_t nthreads) {
+    for (uint64_t i = tid; i < (uint64_t)nb * n; i += nthreads) {
+        uint32_t b = boxes[i / n], v = (uint32_t)(i % n);
+        uint64_t off = ((uint64_t)b * n + v) * P + (v >> 6);
+        NT[off] |= 1ull << (v & 63);
+        dNT[off] |= 1ull << (v & 63);
+        if (rank) rank[((uint64_t)b * n + v) * n + v] = 0;
+    }
+    for (uint64_t i = tid; i < (uint64_t)nb * Pn; i += nthreads) {
+        uint32_t b = boxes[i / Pn], k = (uint32_t)(i % Pn);
+        uint32_t hi = n - k * 64;
+        dnt_act[(uint64_t)b * Pn + k] = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+    }
+}
+
+__global__ void k_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
+                      uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb) {
+    eps_body(NT, dNT, dnt_act, rank, n, P, Pn, boxes, nb,
+             (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, (uint64_t)gridDim.x * blockDim.x);
+}
+
+hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
+                      uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb, hipStream_t s) {
+    if (!nb) return hipSuccess;
+    hipLaunchKernelGGL(k_eps, dim3(grid_for((uint64_t)nb * n)), dim3(kBlock), 0, s, NT, dNT,
+                       dnt_act, rank, n, P, Pn, boxes, nb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// closure row: the core of both the Kronecker seeding and a closure level
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t *row,
+                                       uint32_t pass0, uint32_t gw, int lane) {
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        uint32_t w = pass0 + c * kWave + lane;
+        if (w < gw) acc[c] |= row[c * kWave + lane];
+    }
+}
+
+// One wavefront computes the new source bits of product row (f, v) over the
+// source tile of a.  SEED: the OR runs over the new graph edges only (the
+// Kronecker product with A2: every graph edge in the first iteration, the
+// previous write-back's dNT afterwards) and takes whole closure rows T as
+// the rows that now reach further.  LEVEL: the OR runs over all edges (the
+// current M2) and takes the frontier rows D of the previous level.  Either
+// way the result, masked by what T already holds, is the "custom AND" of
+// Sec. 3.1.1 (0 AND 1 = 1, else 0): exactly the bits that are new.
+// Returns (wave-uniformly) whether the row gained a bit; adds the number of
+// new bits to cnt (per lane); fed tells whether any source row fed the row.
+template <bool SEED>
+__device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned long long &cnt,
+                           bool &fed) {
+    const int lane = __lane_id();
+    const uint32_t tb = a.in_off[f], te = a.in_off[f + 1];
+    fed = false;
+    if (tb == te) return false;
+    bool row_new = false;
+    for (uint32_t pass0 = 0; pass0 < a.gw; pass0 += kChunks * kWave) {
+        uint64_t acc[kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) acc[c] = 0;
+        for (uint32_t t = tb; t < te; ++t) {
+            const InTrans tr = a.in_tr[t];
+            const uint64_t *rows = a.src + (uint64_t)tr.src * a.n * a.src_pitch + a.src_off + pass0;
+            const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
+            if (tr.sym < a.n_terms) {
+                if (SEED && !a.seed_terms) continue;
+                const uint32_t *op = a.goff + (uint64_t)tr.sym * (a.n + 1) + v;
+                const uint32_t b = op[0], e = op[1];
+                for (uint32_t base = b; base < e; base += kWave) {
+                    uint32_t x = 0;
+                    bool ok = false;
+                    if (base + lane < e) {
+                        x = a.gidx[base + lane];
+                        ok = test_bit(sact, x);
+                    }
+                    uint64_t m = __ballot(ok);
+                    fed |= (m != 0);
+                    while (m) {
+                        const int j = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const uint32_t xj = (uint32_t)__builtin_amdgcn_readlane((int)x, j);
+                        or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane);
+                    }
+                }
+            } else {
+                const uint32_t N = tr.sym - a.n_terms;
+                if (SEED && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
+                const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
+                for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
+                    const uint32_t k = k0 + lane;
+                    uint64_t wb = 0;
+                    if (k < a.Pn) wb = sel[k] & sact[k];
+                    uint64_t m = __ballot(wb != 0);
+                    fed |= (m != 0);
+                    while (m) {
+                        const int j = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        uint64_t bits = readlane64(wb, j);
+                        while (bits) {
+                            const int bb = __ffsll((unsigned long long)bits) - 1;
+                            bits &= bits - 1;
+                            const uint32_t xj = (k0 + (uint32_t)j) * 64u + (uint32_t)bb;
+                            or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane);
+                        }
+                    }
+                }
+            }
+        }
+        if (!fed) return false;  // no source row feeds (f, v): same in every pass
+        uint64_t *trow = a.T + ((uint64_t)f * a.n + v) * a.P + a.w0 + pass0;
+        uint64_t *drow = a.dn + ((uint64_t)f * a.n + v) * a.G + pass0;
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const uint32_t w = pass0 + c * kWave + lane;
+            if (w < a.gw) {
+                const uint64_t t = trow[c * kWave + lane];
+                const uint64_t nw = acc[c] & ~t;
+                if (nw) {
+                    trow[c * kWave + lane] = t | nw;
+                    any = true;
+                    cnt += (unsigned long long)__popcll(nw);
+                }
+                drow[c * kWave + lane] = nw;
+            }
+        }
+        row_new |= (__ballot(any) != 0);
+    }
+    return row_new;
+}
+
+template <bool SEED>
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+    if (a.slot_prev != kNoSlot && a.ctr[(uint64_t)a.slot_prev * kSlotWords] == 0) return;  // frontier ran dry
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
+    if (a.act_clear)
+        for (uint64_t i = gtid; i < a.clear_words; i += gthreads) a.act_clear[i] = 0;
+    const int lane = __lane_id();
+    const uint64_t wave = gtid >> 6, nwaves = gthreads >> 6;
+    unsigned long long cnt = 0, fed_rows = 0, new_rows = 0;
+    const uint64_t rows = (uint64_t)a.nQ * a.n;
+    for (uint64_t r = wave; r < rows; r += nwaves) {
+        const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
+        bool fed = false;
+        if (gather_row<SEED>(a, f, v, cnt, fed) && lane == 0) {
+            atomicOr((unsigned long long *)&a.actn[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
+            atomicOr((unsigned long long *)&a.tnz[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
+            ++new_rows;
+        }
+        fed_rows += fed ? 1 : 0;
+    }
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+        unsigned long long *c = a.ctr + (uint64_t)a.slot_cur * kSlotWords;
+        if (cnt) atomicAdd(&c[0], cnt);
+        if (fed_rows) atomicAdd(&c[1], fed_rows);
+        if (new_rows) atomicAdd(&c[2], new_rows);
+    }
+}
+
+hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s) {
+    if (seed)
+        hipLaunchKernelGGL(k_gather<true>, dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_gather<false>, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// write-back (Listing 1, after the closure): the pairs (u, v) with a new
+// closure entry from (q_N^0, u) to (f, v), f final in box N, become edges of
+// M2^N; those not already present form A2^N for the next iteration.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N, uint32_t v,
+                                              unsigned long long &cnt_box, bool &any_row) {
+    const int lane = __lane_id();
+    const uint32_t fb = a.fin_off[N], fe = a.fin_off[N + 1];
+    uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
+    uint64_t *dnt = a.dNT + ((uint64_t)N * a.n + v) * a.P;
+    bool any = false;
+    for (uint32_t k = lane; k < a.Pn; k += kWave) {
+        uint64_t acc = 0;
+        for (uint32_t i = fb; i < fe; ++i) acc |= a.T[((uint64_t)a.fin[i] * a.n + v) * a.P + k];
+        const uint64_t old = nt[k];
+        const uint64_t nw = acc & ~old;
+        if (nw) {
+            nt[k] = old | nw;
+            any = true;
+            cnt_box += (unsigned long long)__popcll(nw);
+            if (a.rank) {
+                uint64_t bits = nw;
+                while (bits) {
+                    const int b = __ffsll((unsigned long long)bits) - 1;
+                    bits &= bits - 1;
+                    a.rank[((uint64_t)N * a.n + v) * a.n + (uint64_t)k * 64 + b] = (uint8_t)(a.iter > 255 ? 255 : a.iter);
+                }
+            }
+        }
+        dnt[k] = nw;
+    }
+    any_row = __ballot(any) != 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
+    const int lane = __lane_id();
+    const uint64_t wave = gtid >> 6, nwaves = gthreads >> 6;
+    const uint64_t rows = (uint64_t)a.nB * a.n;
+    for (uint64_t r = wave; r < rows; r += nwaves) {
+        const uint32_t N = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
+        if (a.fin_off[N] == a.fin_off[N + 1]) continue;
+        unsigned long long c = 0;
+        bool any = false;
+        writeback_row(a, N, v, c, any);
+        c = wave_sum(c);
+        if (lane == 0 && any) {
+            atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
+            atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
+        }
+    }
+}
+
+hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_writeback, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// result kernels
+// ---------------------------------------------------------------------------
+__global__ void k_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
+                           unsigned long long *out) {
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long c = 0;
+    for (uint64_t i = gtid; i < rows * words; i += gthreads)
+        c += (unsigned long long)__popcll(p[(i / words) * pitch + (i % words)]);
+    c = wave_sum(c);
+    if (__lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
+                           unsigned long long *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_popcount, dim3(grid_for(rows * words)), dim3(kBlock), 0, s, p, rows, pitch,
+                       words, out);
+    return hipGetLastError();
+}
+
+// NTb: one box's transposed matrix, row v = bits over u.
+__global__ void k_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned long long *out) {
+    const uint32_t Pn = (n + 63) / 64;
+    const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long h = 0;
+    for (uint64_t i = gtid; i < (uint64_t)n * Pn; i += gthreads) {
+        const uint32_t v = (uint32_t)(i / Pn), k = (uint32_t)(i % Pn);
+        uint64_t bits = NTb[(uint64_t)v * P + k];
+        while (bits) {
+            const int b = __ffsll((unsigned long long)bits) - 1;
+            bits &= bits - 1;
+            const uint64_t u = (uint64_t)k * 64 + b;
+            h += splitmix64((u << 32) | v);
+        }
+    }
+    h = wave_sum(h);
+    if (__lane_id() == 0 && h) atomicAdd(out, h);
+}
+
+hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned long long *out,
+                       hipStream_t s) {
+    const uint64_t items = (uint64_t)n * ((n + 63) / 64);
+    hipLaunchKernelGGL(k_hash, dim3(grid_for(items)), dim3(kBlock), 0, s, NTb, n, P, out);
+    return hipGetLastError();
+}
+
+// 64x64 bit-block transpose, one wavefront per block: lane i holds source
+// row (64*vb + i), word ub; ballot of bit j across lanes is destination row
+// (64*ub + j), word vb.
+__global__ __launch_bounds__(kBlock) void k_transpose(const uint64_t *src, uint32_t src_pitch,
+                                                      uint64_t *dst, uint32_t dst_pitch, uint32_t n) {
+    const uint32_t Pn = (n + 63) / 64;
+    const int lane = __lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t blk = wave; blk < (uint64_t)Pn * Pn; blk += nwaves) {
+        const uint32_t vb = (uint32_t)(blk / Pn), ub = (uint32_t)(blk % Pn);
+        const uint32_t v = vb * 64 + lane;
+        const uint64_t word = v < n ? src[(uint64_t)v * src_pitch + ub] : 0ull;
+        uint64_t mine = 0;
+        for (int j = 0; j < 64; ++j) {
+            const uint64_t col = __ballot((word >> j) & 1ull);
+            if (lane == j) mine = col;
+        }
+        const uint32_t u = ub * 64 + lane;
+        if (u < n) dst[(uint64_t)u * dst_pitch + vb] = mine;
+    }
+}
+
+hipError_t launch_transpose(const uint64_t *src, uint32_t src_pitch, uint64_t *dst,
+                            uint32_t dst_pitch, uint32_t n, hipStream_t s) {
+    const uint64_t Pn = (n + 63) / 64;
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for(Pn * Pn * 64)), dim3(kBlock), 0, s, src, src_pitch,
+                       dst, dst_pitch, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused small-graph fixpoint: one workgroup runs the whole loop of Listing 1
+// for one query, with workgroup barriers in place of kernel boundaries.  A
+// persistent grid drains a device queue of queries, so many small queries
+// share one launch.
+// ---------------------------------------------------------------------------
+constexpr int kFusedBlock = 1024;
+constexpr int kFusedMaxBoxes = 64;
+
+__device__ void block_fill(uint64_t *p, uint64_t words) {
+    for (uint64_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+}
+
+__device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
+                          unsigned long long *s_box) {
+    const int lane = __lane_id();
+    const uint32_t wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const uint64_t qwords = (uint64_t)Q.nQ * Q.n * Q.P, bwords = (uint64_t)Q.nB * Q.n * Q.P;
+    block_fill(Q.T, qwords);
+    block_fill(Q.NT, bwords);
+    block_fill(Q.dNT, bwords);
+    block_fill(Q.tnz, (uint64_t)Q.nQ * Q.Pn);
+    block_fill(Q.act, (uint64_t)Q.nQ * Q.Pn);
+    block_fill(Q.actn, (uint64_t)Q.nQ * Q.Pn);
+    block_fill(Q.dnt_act, (uint64_t)Q.nB * Q.Pn);
+    if (threadIdx.x == 0) {
+        Q.stats[0] = 0;
+        Q.stats[1] = 0;
+    }
+    __syncthreads();
+    seed_diag_body(Q.T, Q.tnz, Q.n, Q.P, Q.Pn, Q.starts, Q.nB, threadIdx.x, blockDim.x);
+    __syncthreads();
+    // epsilon initialisation for nullable boxes
+    if (threadIdx.x < Q.nB) s_box[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t b = 0; b < Q.nB; ++b) {
+        if (!Q.nullable[b]) continue;
+        for (uint64_t i = threadIdx.x; i < Q.n; i += blockDim.x) {
+            const uint32_t v = (uint32_t)i;
+            const uint64_t off = ((uint64_t)b * Q.n + v) * Q.P + (v >> 6);
+            Q.NT[off] |= 1ull << (v & 63);
+            Q.dNT[off] |= 1ull << (v & 63);
+            if (Q.rank) Q.rank[((uint64_t)b * Q.n + v) * Q.n + v] = 0;
+        }
+        for (uint64_t k = threadIdx.x; k < Q.Pn; k += blockDim.x) {
+            const uint32_t hi = Q.n - (uint32_t)k * 64;
+            Q.dnt_act[(uint64_t)b * Q.Pn + k] = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+        }
+        if (threadIdx.x == 0) s_box[b] = Q.n;
+    }
+    __syncthreads();
+
+    GatherArgs a;
+    a.n = Q.n; a.P = Q.P; a.Pn = Q.Pn; a.n_terms = Q.n_terms; a.nQ = Q.nQ;
+    a.w0 = 0; a.gw = Q.Pn; a.G = Q.P;
+    a.goff = Q.goff; a.gidx = Q.gidx; a.in_off = Q.in_off; a.in_tr = Q.in_tr;
+    a.T = Q.T; a.tnz = Q.tnz;
+    a.act_clear = nullptr; a.clear_words = 0; a.ctr = nullptr;
+    a.slot_prev = kNoSlot; a.slot_cur = 0;
+
+    WritebackArgs wb;
+    wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
+    wb.T = Q.T; wb.NT = Q.NT; wb.dNT = Q.dNT; wb.dnt_act = Q.dnt_act; wb.rank = Q.rank;
+    wb.ctr = nullptr; wb.slot_base = 0;
+
+    uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
+    uint32_t it = 0;
+    unsigned long long status = 0;
+    for (;;) {
+        ++it;
+        if (Q.max_iters && it > Q.max_iters) {
+            status = 1;
+            break;
+        }
+        bool can_seed = (it == 1);
+        for (uint32_t b = 0; b < Q.nB; ++b) can_seed |= (s_box[b] != 0 && Q.box_used[b]);
+        if (!can_seed) {
+            if (it - 1 < Q.stats_cap && threadIdx.x == 0) Q.stats[2 + it - 1] = 0;
+            break;
+        }
+        // Kronecker product with the new edges
+        a.sel = Q.dNT; a.sel_act = Q.dnt_act; a.src = Q.T; a.src_pitch = Q.P; a.src_off = 0;
+        a.src_act = Q.tnz; a.dn = Dn; a.actn = actn; a.seed_terms = (it == 1);
+        if (threadIdx.x == 0) *s_cnt = 0;
+        __syncthreads();
+        unsigned long long cnt = 0;
+        for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
+            const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+            bool fed;
+            if (gather_row<true>(a, f, v, cnt, fed) && lane == 0) {
+                atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+            }
+        }
+        cnt = wave_sum(cnt);
+        if (lane == 0 && cnt) atomicAdd(s_cnt, cnt);
+        __syncthreads();
+        // incremental closure: frontier levels until no new bit
+        while (*s_cnt != 0) {
+            uint64_t *t = D; D = Dn; Dn = t;
+            t = act; act = actn; actn = t;
+            block_fill(actn, (uint64_t)Q.nQ * Q.Pn);
+            __syncthreads();
+            if (threadIdx.x == 0) *s_cnt = 0;
+            __syncthreads();
+            a.sel = Q.NT; a.sel_act = nullptr; a.src = D; a.src_pitch = Q.P; a.src_off = 0;
+            a.src_act = act; a.dn = Dn; a.actn = actn;
+            cnt = 0;
+            for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
+                const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                bool fed;
+                if (gather_row<false>(a, f, v, cnt, fed) && lane == 0) {
+                    atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                }
+            }
+            cnt = wave_sum(cnt);
+            if (lane == 0 && cnt) atomicAdd(s_cnt, cnt);
+            __syncthreads();
+        }
+        // write-back
+        block_fill(Q.dnt_act, (uint64_t)Q.nB * Q.Pn);
+        if (threadIdx.x < Q.nB) s_box[threadIdx.x] = 0;
+        __syncthreads();
+        wb.iter = it;
+        for (uint64_t r = wave; r < (uint64_t)Q.nB * Q.n; r += nwaves) {
+            const uint32_t N = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+            if (Q.fin_off[N] == Q.fin_off[N + 1]) continue;
+            unsigned long long c = 0;
+            bool any = false;
+            writeback_row(wb, N, v, c, any);
+            c = wave_sum(c);
+            if (lane == 0 && any) {
+                atomicOr((unsigned long long *)&Q.dnt_act[(uint64_t)N * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                atomicAdd(&s_box[N], c);
+            }
+        }
+        __syncthreads();
+        unsigned long long delta = 0;
+        for (uint32_t b = 0; b < Q.nB; ++b) delta += s_box[b];
+        if (threadIdx.x == 0 && it - 1 < Q.stats_cap) Q.stats[2 + it - 1] = delta;
+        if (delta == 0) break;
+        // next iteration starts with empty frontier buffers
+        block_fill(actn, (uint64_t)Q.nQ * Q.Pn);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        Q.stats[0] = it;
+        Q.stats[1] = status;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kFusedBlock) void k_fused(const FusedQuery *qs, uint32_t n_queries,
+                                                      uint32_t *next_query) {
+    __shared__ uint32_t s_q;
+    __shared__ unsigned long long s_cnt;
+    __shared__ unsigned long long s_box[kFusedMaxBoxes];
+    for (;;) {
+        if (threadIdx.x == 0) s_q = atomicAdd(next_query, 1u);
+        __syncthreads();
+        const uint32_t qi = s_q;
+        __syncthreads();
+        if (qi >= n_queries) return;
+        run_fused(qs[qi], &s_cnt, s_box);
+    }
+}
+
+hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query,
+                        hipStream_t s) {
+    uint32_t grid = n_queries < 1024 ? n_queries : 1024;
+    if (!grid) return hipSuccess;
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kFusedBlock), 0, s, qs_dev, n_queries, next_query);
+    return hipGetLastError();
+}
+
+}  // namespace cfpq

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  All arithmetic is Boolean, so every comparison is
+bit-exact: pair bitmaps, counts, order-independent hashes, iteration counts
+where the paper fixes them."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2103_14688_amd import cfpq, rsm as rsm_mod
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+STRATS = [cfpq.STRATEGY_LEVELS, cfpq.STRATEGY_FUSED]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    cfpq.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def run(g, R, **kw):
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    res = cfpq.query(graph, q, **kw)
+    return graph, q, res
+
+
+def check_box(res, bm_oracle, n, box=0):
+    bm = res.bitmap(box)
+    assert H.padding_clear(bm, n)
+    if not np.array_equal(bm, bm_oracle):
+        diff = H.bits_to_pairs(bm, n) ^ H.bits_to_pairs(bm_oracle, n)
+        raise AssertionError(f"bitmaps differ in {len(diff)} pairs, e.g. {sorted(diff)[:5]}")
+    assert res.count(box) == H.popcount(bm_oracle)
+    assert res.hash(box) == H.bitmap_hash(bm_oracle, n)
+
+
+# ---------------------------------------------------------------------------
+# the paper's worked example (Sec. 3.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("strategy", STRATS)
+@pytest.mark.parametrize("figure_rsm", [True, False])
+def test_paper_example(strategy, figure_rsm):
+    fx = json.load(open(os.path.join(GOLDEN, "paper_example.json")))
+    g = synth.make_graph(fx["n"], [tuple(e) for e in fx["edges"]], fx["labels"])
+    R = rsm_mod.paper_example_rsm(g.labels) if figure_rsm else rsm_mod.from_grammar(fx["grammar"], g.labels)
+    _, _, res = run(g, R, strategy=strategy, keep_rank=True)
+    assert {tuple(p) for p in res.pairs(0).tolist()} == {tuple(p) for p in fx["S"]}
+    it, deltas, _ = res.stats()
+    assert it == fx["iterations"]
+    assert deltas == fx["new_nonterminal_edges_per_iteration"]
+    # witnesses: valid paths spelling words of the language
+    edges = {tuple(e) for e in fx["edges"]}
+    for u, v in fx["S"]:
+        path = res.extract_path(u, v)
+        assert path[0][0] == u and path[-1][2] == v
+        word = [g.labels[int(l)] for _, l, _ in path]
+        k = len(word) // 2
+        assert word == ["a"] * k + ["b"] * k and k >= 1
+        assert all((int(a), g.labels[int(l)], int(b)) in edges for a, l, b in path)
+
+
+# ---------------------------------------------------------------------------
+# closed forms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 3, 9])
+@pytest.mark.parametrize("strategy", STRATS)
+def test_chain_anbn(k, strategy):
+    g = synth.chain("a" * k + "b" * k)
+    _, _, res = run(g, rsm_mod.from_grammar(synth.BRACKETS, g.labels), strategy=strategy)
+    assert {tuple(p) for p in res.pairs(0).tolist()} == {(k - j, k + j) for j in range(1, k + 1)}
+    it, deltas, _ = res.stats()
+    assert it == k + 1 and deltas == [1] * k + [0]
+
+
+def test_same_generation_closed_form():
+    g, depth = synth.hierarchy(3000, with_type=False, seed=5)
+    _, _, res = run(g, rsm_mod.from_grammar(synth.SAME_GEN_SC, g.labels))
+    levels = np.bincount(depth)
+    assert res.count(0) == int((levels[1:] ** 2).sum())
+    bm = res.bitmap(0)
+    bits = np.unpackbits(bm.view(np.uint8), axis=1, bitorder="little")[:, :g.n].astype(bool)
+    assert np.array_equal(bits, (depth[:, None] == depth[None, :]) & (depth[:, None] >= 1))
+
+
+# ---------------------------------------------------------------------------
+# balanced brackets on Erdos-Renyi n = 256 (the plain single-query workload)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [synth.BASE_SEED + 1] + [synth.BASE_SEED + 1 + 100 + i for i in range(10)])
+@pytest.mark.parametrize("strategy", STRATS)
+def test_brackets_er256(seed, strategy):
+    g = synth.erdos_renyi(256, seed=seed)
+    want = H.oracle_grammar(g, synth.BRACKETS)["S"][1]
+    _, _, res = run(g, rsm_mod.from_grammar(synth.BRACKETS, g.labels), strategy=strategy)
+    check_box(res, want, g.n)
+
+
+def test_brackets_er256_strategies_same_iterations():
+    g = synth.erdos_renyi(256, seed=synth.BASE_SEED + 1)
+    R = rsm_mod.from_grammar(synth.BRACKETS, g.labels)
+    a = run(g, R, strategy=cfpq.STRATEGY_LEVELS)[2].stats()
+    b = run(g, R, strategy=cfpq.STRATEGY_FUSED)[2].stats()
+    assert a[0] == b[0] and a[1] == b[1]
+
+
+# ---------------------------------------------------------------------------
+# regular path queries on power-law graphs, with source tiling
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n,tile", [(2000, 0), (2000, 1), (2000, 7), (4100, 16), (129, 0), (65, 1)])
+@pytest.mark.parametrize("minimize", [True, False])
+def test_rpq_powerlaw(n, tile, minimize):
+    g = synth.powerlaw(n, seed=synth.BASE_SEED + 2 + n)
+    want = H.oracle_regex(g, synth.RPQ_C2)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels, minimize=minimize)
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, keep_blocks=True)
+    check_box(res, want, g.n)
+    it, deltas, _ = res.stats()
+    # a regular query has one productive iteration (Sec. 3.1.2)
+    assert it == 2 and deltas[1] == 0 and deltas[0] == H.popcount(want)
+    # the start -> final block equals the answer when the box has one final state
+    finals = np.nonzero(R.is_final)[0]
+    if len(finals) == 1:
+        assert np.array_equal(res.block(int(R.box_start[0]), int(finals[0])), want)
+
+
+# ---------------------------------------------------------------------------
+# the paper's CFPQ workload shapes at oracle-friendly sizes
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("tile", [0, 3])
+def test_same_generation_g1(seed, tile):
+    g, _ = synth.hierarchy(2500, seed=synth.BASE_SEED + 3 + seed)
+    want = H.oracle_grammar(g, synth.SAME_GEN_G1)["S"][1]
+    _, _, res = run(g, rsm_mod.from_grammar(synth.SAME_GEN_G1, g.labels), tile_words=tile)
+    check_box(res, want, g.n)
+
+
+def test_same_generation_g2():
+    g, _ = synth.hierarchy(2000, seed=synth.BASE_SEED + 33)
+    want = H.oracle_grammar(g, synth.SAME_GEN_G2)["S"][1]
+    _, _, res = run(g, rsm_mod.from_grammar(synth.SAME_GEN_G2, g.labels))
+    check_box(res, want, g.n)
+
+
+@pytest.mark.parametrize("n", [1500, 4000])
+def test_memory_alias(n):
+    g = synth.clustered(n, cluster=(16, 64), seed=synth.BASE_SEED + 4 + n)
+    want = H.oracle_grammar(g, synth.MEM_ALIAS, ["S", "V"])
+    R = rsm_mod.from_grammar(synth.MEM_ALIAS, g.labels)
+    _, _, res = run(g, R)
+    check_box(res, want["S"][1], g.n, R.box("S"))
+    check_box(res, want["V"][1], g.n, R.box("V"))
+
+
+# ---------------------------------------------------------------------------
+# random queries on small random graphs
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(24))
+def test_random_queries(seed):
+    rng = np.random.default_rng(5000 + seed)
+    labels = [f"l{i}" for i in range(6)]
+    n = int(rng.integers(1, 300))
+    g = synth.powerlaw(max(n, 2), labels=tuple(labels), mean_deg=float(rng.uniform(1, 4)), seed=seed) if n > 1 \
+        else synth.make_graph(1, [(0, "l0", 0)], labels)
+    use = [str(x) for x in rng.choice(labels, size=4, replace=False)]
+    if seed % 2:
+        text = synth.random_regex(rng, use)
+        want = H.oracle_regex(g, text)
+        R = rsm_mod.from_regex(text, g.labels)
+    else:
+        text = synth.random_cfg(rng, use)
+        want = H.oracle_grammar(g, text)["N0"][1]
+        R = rsm_mod.from_grammar(text, g.labels)
+    for strategy in STRATS:
+        _, _, res = run(g, R, strategy=strategy)
+        check_box(res, want, g.n)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_single_vertex_self_loop_nullable():
+    g = synth.make_graph(1, [(0, "a", 0)], ["a", "b"])
+    for text, want in [("S -> a S | eps", {(0, 0)}), ("S -> b", set()), ("S -> a a a", {(0, 0)})]:
+        for strategy in STRATS:
+            _, _, res = run(g, rsm_mod.from_grammar(text, g.labels), strategy=strategy)
+            assert {tuple(p) for p in res.pairs(0).tolist()} == want, text
+
+
+def test_empty_graph():
+    g = synth.make_graph(70, [], ["a"])
+    for text, cnt in [("S -> a S | eps", 70), ("S -> a", 0)]:
+        for strategy in STRATS:
+            _, _, res = run(g, rsm_mod.from_grammar(text, g.labels), strategy=strategy)
+            assert res.count(0) == cnt
+            assert H.padding_clear(res.bitmap(0), 70)
+
+
+def test_query_terminal_missing_from_graph():
+    g = synth.powerlaw(300, labels=("a", "b"), seed=3)
+    text = "S -> a zz | b"
+    want = H.oracle_grammar(g, text)["S"][1]
+    _, _, res = run(g, rsm_mod.from_grammar(text, g.labels))
+    check_box(res, want, g.n)
+
+
+def test_max_iters_limit():
+    g = synth.chain("aaaabbbb")
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(rsm_mod.from_grammar(synth.BRACKETS, g.labels))
+    for strategy in STRATS:
+        with pytest.raises(cfpq.CfpqError) as e:
+            cfpq.query(graph, q, strategy=strategy, max_iters=2)
+        assert e.value.status == cfpq.ERR_LIMIT
+
+
+# ---------------------------------------------------------------------------
+# batch: every result is the same alone and in the mix
+# ---------------------------------------------------------------------------
+def test_batch_alone_vs_mix():
+    rng = np.random.default_rng(77)
+    labels = [f"l{i}" for i in range(8)]
+    graphs, queries, wants = [], [], []
+    for i in range(12):
+        n = int(rng.choice([100, 500, 900, 1500]))
+        g = synth.powerlaw(n, labels=tuple(labels), mean_deg=3.0, seed=100 + i)
+        use = [str(x) for x in rng.choice(labels, size=5, replace=False)]
+        text = synth.random_regex(rng, use) if i % 2 else synth.random_cfg(rng, use)
+        R = rsm_mod.from_regex(text, labels) if i % 2 else rsm_mod.from_grammar(text, labels)
+        graphs.append(cfpq.Graph.from_synth(g))
+        queries.append(cfpq.Query(R))
+        wants.append((H.oracle_regex(g, text) if i % 2 else H.oracle_grammar(g, text)["N0"][1], n))
+    mix = cfpq.query_batch(graphs, queries)
+    for (want, n), res, gr, q in zip(wants, mix, graphs, queries):
+        alone = cfpq.query(gr, q)
+        assert np.array_equal(res.bitmap(0), want)
+        assert np.array_equal(alone.bitmap(0), want)
+        assert res.stats()[:2] == alone.stats()[:2]
