@@ -23,6 +23,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the level kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE passes (scaled by a 1 GiB copy kernel: fetch x2.0, write x1.0),
+# keyed by the library version they were taken on; see profiles/.  A kernel
+# change bumps the version and the figure is reported as null until the
+# counters are taken again.
+PMC_TRAFFIC = {"cfpq-gfx950 0.1": 3.4596e9}
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -33,6 +40,9 @@ def main():
     ap.add_argument("--tile-words", type=int, default=0)
     ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 3 times (reference kernel for the "
+                         "FETCH_SIZE/WRITE_SIZE scale factor) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding is "
@@ -41,6 +51,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        a = torch.ones(args.calibrate_copy * (1 << 20) // 8, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 8, "copies": 3}), flush=True)
+        return
 
     import synth
     from paper_2103_14688_amd import cfpq, rsm
@@ -122,7 +141,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC.get(cfpq.cfpq_version()),
             "kernel": "k_gather<false> (closure frontier level)",
             "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
         },
