@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--tile-words", type=int, default=0)
     ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--serve-nmax", type=int, default=20000)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (reference kernel for the "
                          "FETCH_SIZE/WRITE_SIZE scale factor) and exit")
@@ -116,6 +119,8 @@ def main():
                "sample": f"{len(srcs)} of {g.n} sources (product-automaton BFS per source), "
                          f"{cpu_pairs} pairs in {dt:.2f} s"}
 
+    serving = None if args.no_serve else measure_serving(args)
+
     out = {
         "metric": "reachable pairs/s (fixpoint, plain single query)",
         "value": pairs * args.steps / wall,
@@ -146,8 +151,84 @@ def main():
             "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def measure_serving(args):
+    """Batched vs plain on the serving mix: 64 resident power-law graphs
+    (n log-uniform in [1000, serve_nmax], mean out-degree 3, 8 Zipf labels),
+    random regex / normal-form grammar queries.  Closed loop (all requests at
+    t = 0) gives throughput; an open loop with Poisson arrivals at 0.7x the
+    plain throughput gives p50/p99 latency.  Every batched answer is compared
+    with the plain one (count, hash, iterations)."""
+    import numpy as np
+
+    import synth
+    from paper_2103_14688_amd import cfpq, rsm, serve
+
+    labels, recipes, qs = synth.serving_mix(n_graphs=64, n_queries=args.serve_queries,
+                                            n_range=(1000, args.serve_nmax))
+    graphs = [synth.serving_graph(n, seed, labels) for n, seed in recipes]
+    handles = [cfpq.Graph.from_synth(g) for g in graphs]
+    comp = []
+    for gi, kind, text in qs:
+        R = rsm.from_regex(text, labels) if kind == "regex" else rsm.from_grammar(text, labels)
+        comp.append((gi, R, cfpq.Query(R)))
+
+    def requests():
+        return [serve.Request(i, handles[gi], q, graphs[gi].n, R.n_states, R.n_boxes)
+                for i, (gi, R, q) in enumerate(comp)]
+
+    backend = serve.GpuBackend()
+
+    def run(mode, arrivals=None):
+        srv = serve.Server(backend, mode=mode, slots=4)
+        rs = requests()
+        t0 = time.perf_counter()
+        if arrivals is None:
+            for r in rs:
+                srv.submit(r)
+            srv.drain()
+        else:
+            serve.replay(srv, rs, arrivals)
+        wall = time.perf_counter() - t0
+        srv.close()
+        bad = [r.error for r in rs if r.error]
+        assert not bad, bad[:3]
+        return rs, wall, srv
+
+    print(f"# serving: {len(comp)} queries on 64 graphs, n <= {args.serve_nmax}", file=sys.stderr, flush=True)
+    run("batched")                                   # warm-up (allocator, code objects)
+    plain, wall_p, _ = run("plain")
+    batched, wall_b, srv_b = run("batched")
+    same = all(a.result == b.result for a, b in zip(plain, batched))
+    pairs = sum(r.result[0] for r in plain)
+    mu = len(plain) / wall_p
+    lam = 0.7 * mu
+    arr = np.cumsum(np.random.default_rng(synth.BASE_SEED + 9).exponential(1.0 / lam, size=len(comp)))
+    plain_o, _, _ = run("plain", arr)
+    batched_o, _, _ = run("batched", arr)
+    pp = serve.percentiles([r.latency for r in plain_o])
+    pb = serve.percentiles([r.latency for r in batched_o])
+    return {
+        "workload": f"{len(comp)} queries (half regex, half CFG) on 64 resident power-law graphs, "
+                    f"n log-uniform in [1000, {args.serve_nmax}]",
+        "closed_loop": {
+            "plain_queries_per_s": mu, "batched_queries_per_s": len(batched) / wall_b,
+            "plain_pairs_per_s": pairs / wall_p, "batched_pairs_per_s": pairs / wall_b,
+            "speedup": wall_p / wall_b, "batched_launch_groups": srv_b.batches,
+            "max_concurrent_slots": srv_b.max_concurrent,
+        },
+        "open_loop": {
+            "arrival_rate_per_s": lam,
+            "plain_p50_ms": pp[50] * 1e3, "plain_p99_ms": pp[99] * 1e3,
+            "batched_p50_ms": pb[50] * 1e3, "batched_p99_ms": pb[99] * 1e3,
+        },
+        "answers_identical_alone_vs_mix": same and all(a.result == b.result for a, b in zip(plain_o, batched_o)),
+        "total_pairs": pairs,
+    }
 
 
 if __name__ == "__main__":

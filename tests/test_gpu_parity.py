@@ -246,3 +246,24 @@ def test_batch_alone_vs_mix():
         assert np.array_equal(res.bitmap(0), want)
         assert np.array_equal(alone.bitmap(0), want)
         assert res.stats()[:2] == alone.stats()[:2]
+
+
+# ---------------------------------------------------------------------------
+# full bench size: sampled source rows against the oracle's per-source BFS
+# ---------------------------------------------------------------------------
+def test_rpq_bench_size_sampled_rows():
+    import oracle
+    g = synth.powerlaw(100000, seed=synth.BASE_SEED + 2)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
+    graph, q, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS)
+    bm = res.bitmap(0)
+    assert H.padding_clear(bm, g.n)
+    rng = np.random.default_rng(11)
+    srcs = np.sort(rng.choice(g.n, size=48, replace=False)).astype(np.uint32)
+    srcs = np.concatenate([srcs, np.array([0, g.n - 1], dtype=np.uint32)])
+    want = oracle.rpq_rows(g.n, g.src, g.lbl, g.dst, g.labels, synth.RPQ_C2, srcs, threads=8)
+    assert np.array_equal(bm[srcs], want)
+    # whole-answer invariants: count = popcount = first iteration's delta
+    it, deltas, _ = res.stats()
+    total = int(np.unpackbits(bm.view(np.uint8)).sum())
+    assert res.count(0) == total == deltas[0] and it == 2
