@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 # keyed by the library version they were taken on; see profiles/.  A kernel
 # change bumps the version and the figure is reported as null until the
 # counters are taken again.
-PMC_TRAFFIC = {"cfpq-gfx950 0.1": 3.4596e9}
+PMC_TRAFFIC = {("cfpq-gfx950 0.1", "levels"): 3.4596e9}
 
 
 def main():
@@ -38,6 +38,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tile-words", type=int, default=0)
+    ap.add_argument("--strategy", choices=["auto", "levels", "condensed"], default="auto",
+                    help="closure strategy of the plain single-query path (auto = condensed for a regular query)")
     ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400)
@@ -73,7 +75,10 @@ def main():
     R = rsm.from_regex(synth.RPQ_C2, g.labels)
     graph = cfpq.Graph.from_synth(g)
     q = cfpq.Query(R)
-    kw = dict(strategy=cfpq.STRATEGY_LEVELS, tile_words=args.tile_words)
+    strat = {"auto": cfpq.STRATEGY_AUTO, "levels": cfpq.STRATEGY_LEVELS,
+             "condensed": cfpq.STRATEGY_CONDENSED}[args.strategy]
+    kw = dict(strategy=strat, tile_words=args.tile_words)
+    dominant = cfpq.KERNEL_LEVEL if args.strategy == "levels" else cfpq.KERNEL_COND_LEVEL
     print(f"# graph n={g.n} m={len(g.src)} states={R.n_states}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
@@ -93,12 +98,13 @@ def main():
     # dominant kernel: closure level launches, summed over the timed steps
     lv_n = lv_ms = lv_bytes = 0
     for r in results:
-        n_l, ms_l, by_l = r.profile(cfpq.KERNEL_LEVEL)
+        n_l, ms_l, by_l = r.profile(dominant)
         lv_n += n_l
         lv_ms += ms_l
         lv_bytes += by_l
     seed = [r.profile(cfpq.KERNEL_SEED) for r in results]
     wb = [r.profile(cfpq.KERNEL_WRITEBACK) for r in results]
+    scc = [r.profile(cfpq.KERNEL_COND_SCC) for r in results]
     for r in results:
         r.close()
     avg_launch_ms = lv_ms / max(lv_n, 1)
@@ -141,13 +147,17 @@ def main():
             "iterations": it, "fixpoint_ms_median": float(np.median(fix)), "fixpoint_ms_mean": float(np.mean(fix)),
             "tile_words": args.tile_words,
             "level_launches_per_step": lv_n / args.steps,
+            "strategy": args.strategy,
+            "component_search_ms_per_step": sum(s[1] for s in scc) / args.steps,
             "seed_ms_per_step": sum(s[1] for s in seed) / args.steps,
             "writeback_ms_per_step": sum(w[1] for w in wb) / args.steps,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC.get(cfpq.cfpq_version()),
-            "kernel": "k_gather<false> (closure frontier level)",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": PMC_TRAFFIC.get((cfpq.cfpq_version(), args.strategy)),
+            "kernel": "k_gather<false> (closure frontier level)" if args.strategy == "levels"
+                      else "k_cond_level (one topological level of the component graph)",
             "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "cpu_baseline": cpu,

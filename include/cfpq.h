@@ -129,7 +129,13 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  * Options (NULL = defaults):
  *   strategy   : CFPQ_STRATEGY_AUTO, _LEVELS (one launch per closure level,
  *                any size), _FUSED (one workgroup runs the whole fixpoint;
- *                small graphs only, CFPQ_ERR_LIMIT beyond its size limit).
+ *                small graphs only, CFPQ_ERR_LIMIT beyond its size limit),
+ *                _CONDENSED (closure through the strongly connected
+ *                components of the product graph, each component's row
+ *                computed once in topological order; only for RSMs without
+ *                box-labelled transitions, i.e. regular queries, else
+ *                CFPQ_ERR_INVALID).  AUTO picks FUSED for small graphs,
+ *                CONDENSED for other regular queries, LEVELS otherwise.
  *   max_iters  : 0 = no limit beyond the natural bound; otherwise the query
  *                fails with CFPQ_ERR_LIMIT if the loop has not stopped after
  *                max_iters iterations.
@@ -144,7 +150,7 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  * Errors: CFPQ_ERR_INVALID if the RSM uses more terminals than the graph
  *   has labels; CFPQ_ERR_OOM; CFPQ_ERR_DEVICE; CFPQ_ERR_LIMIT.
  * ---------------------------------------------------------------------- */
-enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2 };
+enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2, CFPQ_STRATEGY_CONDENSED = 3 };
 
 typedef struct {
     uint32_t strategy;
@@ -222,8 +228,13 @@ cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_
  * for a level launch 8 * tile_words * (R_in + 3 * R_out), R_in the frontier
  * rows read and R_out the target rows fed by them (read T, write T and the
  * next frontier); for a write-back 8 * ceil(n/64) * (|F_N| + 3) per row of
- * each box.  CFPQ_ERR_INVALID if the query was not profiled. */
-enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2 };
+ * each box; for a condensed level (CFPQ_KERNEL_COND_LEVEL, one topological
+ * level of the component graph) 8 * ceil(n/64) * 2 per component completed
+ * (its row written once and read once); CFPQ_KERNEL_COND_SCC sums the
+ * component search (no byte count).  CFPQ_ERR_INVALID if the query was not
+ * profiled. */
+enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2, CFPQ_KERNEL_COND_LEVEL = 3,
+       CFPQ_KERNEL_COND_SCC = 4 };
 cfpq_status cfpq_result_profile(cfpq_result res, uint32_t kind, uint64_t *launches, double *ms,
                                 uint64_t *bytes);
 

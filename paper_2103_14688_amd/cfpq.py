@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcfpq.so")
 
 OK, ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_NOT_FOUND, ERR_BUFFER, ERR_LIMIT, ERR_REJECTED = 0, -1, -2, -3, -4, -5, -6, -7
 ADD_INVERSES = 1
-STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED = 0, 1, 2
+STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED, STRATEGY_CONDENSED = 0, 1, 2, 3
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUFFER", -6: "LIMIT",
            -7: "REJECTED"}
@@ -251,7 +251,7 @@ def cfpq_result_stats(res, cap=4096):
     return it.value, d[: min(it.value, cap)].tolist(), ms.value
 
 
-KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK = 0, 1, 2
+KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK, KERNEL_COND_LEVEL, KERNEL_COND_SCC = 0, 1, 2, 3, 4
 
 
 def cfpq_result_profile(res, kind):

@@ -105,6 +105,7 @@ struct cfpq_graph_s {
     uint64_t n_edges = 0;
     Alloc alloc;
     DevBuf off, idx;                         // CSC per label (predecessors)
+    DevBuf soff, sidx;                       // CSR per label (successors)
     std::vector<uint32_t> h_out_off, h_out;  // CSR per label (successors), host
 };
 
@@ -133,7 +134,7 @@ struct cfpq_result_s {
     struct Prof {
         uint64_t launches = 0, bytes = 0;
         double ms = 0.0;
-    } prof[3];
+    } prof[5];
     bool profiled = false;
 };
 
@@ -224,11 +225,16 @@ extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const ui
             }
     }
     if (!g->off.alloc(&g->alloc, noff * sizeof(uint32_t), s) ||
-        !g->idx.alloc(&g->alloc, idx.size() * sizeof(uint32_t), s))
+        !g->idx.alloc(&g->alloc, idx.size() * sizeof(uint32_t), s) ||
+        !g->soff.alloc(&g->alloc, noff * sizeof(uint32_t), s) ||
+        !g->sidx.alloc(&g->alloc, idx.size() * sizeof(uint32_t), s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (graph)");
     HIP_TRY(hipMemcpyAsync(g->off.p, off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    if (!idx.empty())
+    HIP_TRY(hipMemcpyAsync(g->soff.p, g->h_out_off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    if (!idx.empty()) {
         HIP_TRY(hipMemcpyAsync(g->idx.p, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(g->sidx.p, g->h_out.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
     *out = g.release();
     return CFPQ_OK;
@@ -302,8 +308,9 @@ constexpr uint32_t kStatsCap = 4096;
 
 struct Plan {
     uint32_t n, Pn, P, nQ, nB, n_terms;
-    std::vector<uint32_t> in_off;
-    std::vector<InTrans> in_tr;
+    std::vector<uint32_t> in_off, out_off;
+    std::vector<InTrans> in_tr, out_tr;   // out_tr[.].src = target state
+    bool has_calls = false;               // some transition is box-labelled
     std::vector<uint32_t> starts;     // box start per box
     std::vector<uint32_t> fin_off, fin;
     std::vector<uint32_t> eps_boxes;  // boxes whose start is final
@@ -324,6 +331,13 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     p.in_tr.resize(r.t_src.size());
     std::vector<uint32_t> fill(p.in_off.begin(), p.in_off.end() - 1);
     for (size_t i = 0; i < r.t_src.size(); ++i) p.in_tr[fill[r.t_dst[i]]++] = InTrans{r.t_src[i], r.t_sym[i]};
+    p.out_off.assign(p.nQ + 1, 0);
+    for (size_t i = 0; i < r.t_src.size(); ++i) p.out_off[r.t_src[i] + 1]++;
+    for (uint32_t q = 0; q < p.nQ; ++q) p.out_off[q + 1] += p.out_off[q];
+    p.out_tr.resize(r.t_src.size());
+    std::vector<uint32_t> ofill(p.out_off.begin(), p.out_off.end() - 1);
+    for (size_t i = 0; i < r.t_src.size(); ++i) p.out_tr[ofill[r.t_src[i]]++] = InTrans{r.t_dst[i], r.t_sym[i]};
+    for (size_t i = 0; i < r.t_sym.size(); ++i) p.has_calls |= r.t_sym[i] >= r.n_terms;
     p.starts = r.box_start;
     p.fin_off.assign(p.nB + 1, 0);
     for (uint32_t q = 0; q < p.nQ; ++q)
@@ -349,8 +363,8 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
 struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
-             *eps = nullptr;
-    InTrans *in_tr = nullptr;
+             *eps = nullptr, *out_off = nullptr;
+    InTrans *in_tr = nullptr, *out_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
 
@@ -370,6 +384,8 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     size_t o_eps = put(p.eps_boxes.data(), p.eps_boxes.size() * 4);
     size_t o_null = put(p.nullable.data(), p.nullable.size());
     size_t o_used = put(p.box_used.data(), p.box_used.size());
+    size_t o_out_off = put(p.out_off.data(), p.out_off.size() * 4);
+    size_t o_out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
     if (!t.buf.alloc(al, host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
     HIP_TRY(hipMemcpyAsync(t.buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
     uint8_t *b = t.buf.as<uint8_t>();
@@ -381,6 +397,8 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     t.eps = (uint32_t *)(b + o_eps);
     t.nullable = b + o_null;
     t.box_used = b + o_used;
+    t.out_off = (uint32_t *)(b + o_out_off);
+    t.out_tr = (InTrans *)(b + o_out_tr);
     // the host vector dies with this frame: wait for the copy
     HIP_TRY(hipStreamSynchronize(s));
     return CFPQ_OK;
@@ -412,6 +430,10 @@ struct PinnedCounters {
         return true;
     }
 };
+
+uint64_t *d_u64(const DevBuf &b) { return b.as<uint64_t>(); }
+
+bool max_iters_hit(const cfpq_query_opts &o, uint32_t it) { return o.max_iters && it > o.max_iters; }
 
 uint32_t gather_grid(uint64_t rows) {
     uint64_t blocks = (rows + (kBlock / kWave) - 1) / (kBlock / kWave);
@@ -653,6 +675,242 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
 }
 
 // ---------------------------------------------------------------------------
+// CONDENSED strategy: closure through the strongly connected components of
+// the product graph (regular queries: no box-labelled transition)
+// ---------------------------------------------------------------------------
+cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o,
+                          cfpq_result_s &res) {
+    hipStream_t s = (hipStream_t)o.stream;
+    const Alloc *al = &res.alloc;
+    Plan p = make_plan(g, r);
+    if (p.has_calls) return fail(CFPQ_ERR_INVALID, "condensed strategy needs an RSM without box-labelled transitions");
+    if ((uint64_t)p.nQ * p.n >= 0xFFFFFFFFull) return fail(CFPQ_ERR_LIMIT, "product graph exceeds 2^32-1 nodes");
+    Tables tb;
+    cfpq_status st = upload_tables(p, al, s, tb);
+    if (st != CFPQ_OK) return st;
+    const uint32_t n = p.n, P = p.P, Pn = p.Pn, nQ = p.nQ, nB = p.nB;
+    const uint32_t N = nQ * n;
+    const uint64_t qw = (uint64_t)nQ * n * P, bw = (uint64_t)nB * n * P;
+    const uint64_t N64 = ((uint64_t)N + 63) / 64 * 64;   // byte arrays padded to whole words
+    const uint64_t Nu = ((uint64_t)N + 1) / 2 * 2;         // u32 arrays start on 8-byte boundaries
+    constexpr uint32_t kCtr = 8192;
+    if ((uint64_t)nB * kSlotWords > kCtr) return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
+
+    DevBuf T, dNT, dnt_act, u32s, u8s, ctr;
+    if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
+        !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) || !u32s.alloc(al, Nu * 4 * 6 + 64, s) ||
+        !u8s.alloc(al, 2 * N64 + 64, s) || !ctr.alloc(al, (uint64_t)2 * kCtr * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (condensed query)");
+    if (o.keep_rank) {
+        if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
+        HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)nB * n * n, s));
+    }
+    uint32_t *scc = u32s.as<uint32_t>(), *fw = scc + Nu, *bwm = fw + Nu, *color = bwm + Nu, *size = color + Nu,
+             *indeg = size + Nu, *lev = fw;  // lev reuses fw after the search
+    uint8_t *alive = u8s.as<uint8_t>(), *found = alive + N64;
+    unsigned long long *cc = ctr.as<unsigned long long>();
+    unsigned long long *lc = cc + kCtr;   // ring of per-level component counts
+    ProdGraph pg{};
+    pg.n = n; pg.nQ = nQ;
+    pg.goff = g.off.as<uint32_t>(); pg.gidx = g.idx.as<uint32_t>();
+    pg.soff = g.soff.as<uint32_t>(); pg.sidx = g.sidx.as<uint32_t>();
+    pg.in_off = tb.in_off; pg.in_tr = tb.in_tr; pg.out_off = tb.out_off; pg.out_tr = tb.out_tr;
+
+    hipEvent_t ev[4];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+    const bool prof = o.profile != 0;
+    res.profiled = prof;
+
+    PinnedCounters pc;
+    if (!pc.ensure(kCtr)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+    uint32_t slot = 0;
+    // a fresh zeroed counter per launch; the whole array is cleared when used up
+    auto next_slot = [&](uint32_t k) -> cfpq_status {
+        if (slot + k >= kCtr) {
+            HIP_TRY(launch_fill((uint64_t *)cc, kCtr, 0, s));
+            slot = 0;
+        }
+        return CFPQ_OK;
+    };
+    auto read = [&](uint32_t first, uint32_t k) -> cfpq_status {
+        HIP_TRY(hipMemcpyAsync(pc.h, cc + first, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return CFPQ_OK;
+    };
+    // run launch(slot) until a launch counts zero, up to max_rounds
+    auto until_zero = [&](auto launch, uint32_t max_rounds) -> cfpq_status {
+        for (uint32_t i = 0; i < max_rounds; ++i) {
+            cfpq_status st2 = next_slot(1);
+            if (st2 != CFPQ_OK) return st2;
+            HIP_TRY(launch(cc + slot));
+            if ((st2 = read(slot, 1)) != CFPQ_OK) return st2;
+            ++slot;
+            if (pc.h[0] == 0) return CFPQ_OK;
+        }
+        return CFPQ_OK;
+    };
+
+    HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_fill(d_u64(T), qw, 0, s));
+    HIP_TRY(launch_fill(d_u64(res.NT), bw, 0, s));
+    HIP_TRY(launch_fill(d_u64(dNT), bw, 0, s));
+    HIP_TRY(launch_fill(d_u64(dnt_act), (uint64_t)nB * Pn, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)cc, 2 * kCtr, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)u32s.p, (Nu * 4 * 6 + 64) / 8, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)alive, N64 / 8, 0x0101010101010101ull, s));  // every node live
+    HIP_TRY(launch_fill((uint64_t *)found, N64 / 8 + 8, 0, s));
+    HIP_TRY(launch_eps(d_u64(res.NT), d_u64(dNT), d_u64(dnt_act), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
+                       Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+
+    // ---- strongly connected components of the product graph
+    // trimming: nodes with no live predecessor or successor
+    st = until_zero([&](unsigned long long *c) { return launch_trim(pg, alive, scc, c, s); }, 64);
+    if (st != CFPQ_OK) return st;
+    // the component of a high-degree pivot: forward AND backward reachable
+    {
+        if ((st = next_slot(1)) != CFPQ_OK) return st;
+        const uint32_t best_slot = slot++;
+        HIP_TRY(launch_pivot(pg, alive, cc + best_slot, s));
+        if ((st = read(best_slot, 1)) != CFPQ_OK) return st;
+        if (pc.h[0]) {
+            const uint32_t pivot = (uint32_t)(pc.h[0] & 0xFFFFFFFFull);
+            HIP_TRY(launch_set_u32(fw, pivot, 1, s));
+            HIP_TRY(launch_set_u32(bwm, pivot, 1, s));
+            for (int dir = 0; dir < 2; ++dir) {
+                uint32_t *mark = dir ? bwm : fw;
+                for (uint32_t level = 1;; ++level) {
+                    if ((st = next_slot(1)) != CFPQ_OK) return st;
+                    HIP_TRY(launch_reach(pg, alive, mark, level, dir, cc + slot, s));
+                    if ((st = read(slot, 1)) != CFPQ_OK) return st;
+                    ++slot;
+                    if (pc.h[0] == 0) break;
+                }
+            }
+            if ((st = next_slot(1)) != CFPQ_OK) return st;
+            HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, pivot, scc, cc + slot++, s));
+        }
+    }
+    // colouring rounds for the rest
+    for (;;) {
+        if ((st = next_slot(1)) != CFPQ_OK) return st;
+        const uint32_t rem_slot = slot++;
+        HIP_TRY(launch_color_remove(N, alive, found, cc + rem_slot, s));  // counts live nodes
+        if ((st = read(rem_slot, 1)) != CFPQ_OK) return st;
+        if (pc.h[0] == 0) break;
+        HIP_TRY(launch_color_init(N, alive, color, found, s));
+        st = until_zero([&](unsigned long long *c) { return launch_color_prop(pg, alive, color, c, s); }, 0xFFFFFFFFu);
+        if (st != CFPQ_OK) return st;
+        HIP_TRY(launch_color_roots(N, alive, color, found, scc, s));
+        st = until_zero([&](unsigned long long *c) { return launch_color_back(pg, alive, color, found, scc, c, s); },
+                        0xFFFFFFFFu);
+        if (st != CFPQ_OK) return st;
+    }
+    HIP_TRY(hipEventRecord(ev[1], s));
+
+    // ---- condensation, one topological level per launch
+    HIP_TRY(launch_fill((uint64_t *)fw, (Nu * 4 * 2) / 8, 0, s));  // lev (reuses fw/bw) := 0
+    HIP_TRY(launch_cond_count(pg, scc, size, indeg, s));
+    HIP_TRY(launch_cond_seed(n, P, tb.starts, nB, scc, d_u64(T), s));
+    // level L's component count lives in lc[L % kCtr]; the launch for level L
+    // clears lc[(L + 2) % kCtr] before level L + 1 writes it
+    HIP_TRY(launch_cond_roots(N, scc, indeg, lev, lc + 0, s));
+    uint32_t L = 0, hint = 32;
+    uint64_t comps = 0;
+    std::vector<hipEvent_t> lev_ev;   // profiling: an event before each level launch, one after the chunk
+    struct PoolGuard {
+        std::vector<hipEvent_t> *v;
+        ~PoolGuard() {
+            for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+        }
+    } pg_guard{&lev_ev};
+    for (;;) {
+        const uint32_t k = hint;
+        if (prof)
+            while (lev_ev.size() < k + 1) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                lev_ev.push_back(e);
+            }
+        for (uint32_t j = 0; j < k; ++j) {
+            const uint32_t l = L + j;
+            if (prof) HIP_TRY(hipEventRecord(lev_ev[j], s));
+            HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, indeg, lev, d_u64(T), l, lc + l % kCtr,
+                                      lc + (l + 1) % kCtr, lc + (l + 2) % kCtr, s));
+        }
+        if (prof) HIP_TRY(hipEventRecord(lev_ev[k], s));
+        HIP_TRY(hipMemcpyAsync(pc.h, lc, (size_t)kCtr * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (prof)
+            for (uint32_t j = 0; j < k; ++j) {
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, lev_ev[j], lev_ev[j + 1]));
+                res.prof[CFPQ_KERNEL_COND_LEVEL].ms += t;
+            }
+        bool done = false;
+        for (uint32_t j = 0; j <= k; ++j) {
+            const unsigned long long c = pc.h[(L + j) % kCtr];
+            if (c == 0) {
+                done = true;
+                break;
+            }
+            comps += (j < k) ? c : 0;
+        }
+        if (prof) {
+            res.prof[CFPQ_KERNEL_COND_LEVEL].launches += k;
+        }
+        L += k;
+        if (done) break;
+        hint = std::min<uint32_t>(hint * 2, 1024);
+        if (L > 0xFFFFFFFFu - 2048) return fail(CFPQ_ERR_LIMIT, "condensation too deep");
+    }
+    HIP_TRY(hipEventRecord(ev[2], s));
+    // ---- write-back through the component map
+    HIP_TRY(launch_fill(d_u64(dnt_act), (uint64_t)nB * Pn, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)cc, (uint64_t)nB * kSlotWords, 0, s));
+    WritebackArgs w{};
+    w.n = n; w.P = P; w.Pn = Pn; w.nB = nB; w.fin_off = tb.fin_off; w.fin = tb.fin;
+    w.T = d_u64(T); w.NT = d_u64(res.NT); w.dNT = d_u64(dNT); w.dnt_act = d_u64(dnt_act);
+    w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
+    w.iter = 1; w.ctr = cc; w.slot_base = 0; w.row_map = scc;
+    HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
+    if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, d_u64(T), s));
+    HIP_TRY(hipEventRecord(ev[3], s));
+    HIP_TRY(hipMemcpyAsync(pc.h, cc, (size_t)nB * kSlotWords * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    uint64_t delta = 0;
+    for (uint32_t b = 0; b < nB; ++b) delta += pc.h[(size_t)b * kSlotWords];
+    // a second iteration would seed from box-labelled transitions only: none
+    res.deltas.assign({delta, 0});
+    res.iterations = 2;
+    if (max_iters_hit(o, 2)) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+    float ms = 0.f, ms_scc = 0.f, ms_lv = 0.f, ms_wb = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
+    HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms_lv, ev[1], ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms_wb, ev[2], ev[3]));
+    res.ms = ms;
+    if (prof) {
+        res.prof[CFPQ_KERNEL_COND_SCC].launches += 1;
+        res.prof[CFPQ_KERNEL_COND_SCC].ms += ms_scc;
+        (void)ms_lv;
+        res.prof[CFPQ_KERNEL_COND_LEVEL].bytes += 8ull * Pn * 2 * comps;
+        res.prof[CFPQ_KERNEL_WRITEBACK].launches += 1;
+        res.prof[CFPQ_KERNEL_WRITEBACK].ms += ms_wb;
+        for (uint32_t b = 0; b < nB; ++b)
+            res.prof[CFPQ_KERNEL_WRITEBACK].bytes +=
+                8ull * Pn * n * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + (p.fin_off[b + 1] > p.fin_off[b] ? 3 : 0));
+    }
+    if (o.keep_blocks) res.T = std::move(T);
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
 // FUSED strategy: a workgroup per query, many queries per launch
 // ---------------------------------------------------------------------------
 struct FusedJob {
@@ -764,8 +1022,16 @@ cfpq_result_s *new_result(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     return res;
 }
 
+bool has_calls(const cfpq_rsm_s &r) {
+    for (uint32_t sym : r.t_sym)
+        if (sym >= r.n_terms) return true;
+    return false;
+}
+
 cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
-    if (o.strategy > CFPQ_STRATEGY_FUSED) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.strategy > CFPQ_STRATEGY_CONDENSED) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.strategy == CFPQ_STRATEGY_CONDENSED && has_calls(r))
+        return fail(CFPQ_ERR_INVALID, "condensed strategy needs an RSM without box-labelled transitions");
     if (o.keep_rank && g.n > 16384) return fail(CFPQ_ERR_LIMIT, "keep_rank needs n <= 16384");
     if (o.strategy == CFPQ_STRATEGY_FUSED && !fused_ok(g, r))
         return fail(CFPQ_ERR_LIMIT, "fused strategy needs n <= 2048 and at most 64 boxes");
@@ -774,8 +1040,14 @@ cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
 
 bool use_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
     if (o.strategy == CFPQ_STRATEGY_FUSED) return true;
-    if (o.strategy == CFPQ_STRATEGY_LEVELS) return false;
+    if (o.strategy != CFPQ_STRATEGY_AUTO) return false;
     return fused_ok(g, r) && g.n <= 1024;
+}
+
+cfpq_status run_big(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o, cfpq_result_s &res) {
+    const bool cond = o.strategy == CFPQ_STRATEGY_CONDENSED ||
+                      (o.strategy == CFPQ_STRATEGY_AUTO && !has_calls(r) && (uint64_t)r.n_states * g.n < 0xFFFFFFFFull);
+    return cond ? run_condensed(g, r, o, res) : run_levels(g, r, o, res);
 }
 
 }  // namespace
@@ -796,7 +1068,7 @@ extern "C" cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opt
             if ((st = prepare_fused(*g, *r, o, *res, jobs[0])) != CFPQ_OK) return st;
             if ((st = run_fused_jobs(jobs, o, &res->alloc)) != CFPQ_OK) return st;
         } else {
-            if ((st = run_levels(*g, *r, o, *res)) != CFPQ_OK) return st;
+            if ((st = run_big(*g, *r, o, *res)) != CFPQ_OK) return st;
         }
     } catch (const std::bad_alloc &) {
         return fail(CFPQ_ERR_OOM, "host allocation failed");
@@ -831,7 +1103,7 @@ extern "C" cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm
         if ((st = run_fused_jobs(jobs, o, &res[0]->alloc)) != CFPQ_OK) return st;
         jobs.clear();
         for (uint32_t i : big)
-            if ((st = run_levels(*graphs[i], *rsms[i], o, *res[i])) != CFPQ_OK) return st;
+            if ((st = run_big(*graphs[i], *rsms[i], o, *res[i])) != CFPQ_OK) return st;
     } catch (const std::bad_alloc &) {
         return fail(CFPQ_ERR_OOM, "host allocation failed");
     }
@@ -988,8 +1260,8 @@ extern "C" cfpq_status cfpq_result_stats(cfpq_result r, uint32_t *iterations, ui
 extern "C" cfpq_status cfpq_result_profile(cfpq_result r, uint32_t kind, uint64_t *launches, double *ms,
                                            uint64_t *bytes) {
     if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
-    if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile, levels strategy)");
-    if (kind > CFPQ_KERNEL_WRITEBACK) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
+    if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile)");
+    if (kind > CFPQ_KERNEL_COND_SCC) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
     if (launches) *launches = r->prof[kind].launches;
     if (ms) *ms = r->prof[kind].ms;
     if (bytes) *bytes = r->prof[kind].bytes;
@@ -1127,4 +1399,4 @@ extern "C" void cfpq_result_destroy(cfpq_result r) { delete r; }
 
 extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
 
-extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.1"; }
+extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.2"; }

@@ -74,6 +74,7 @@ struct WritebackArgs {
     uint32_t iter;
     unsigned long long *ctr;
     uint32_t slot_base;            // new edges of box N counted at slot_base + N
+    const uint32_t *row_map;       // optional: T row of product node (f, v) is row_map[f*n+v]
 };
 
 // kernels.hip
@@ -92,6 +93,45 @@ hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned lon
 // dst[u][v-word] (row-major, pitch dst_pitch) from src[v][u-word] (pitch src_pitch)
 hipError_t launch_transpose(const uint64_t *src, uint32_t src_pitch, uint64_t *dst,
                             uint32_t dst_pitch, uint32_t n, hipStream_t s);
+
+// Implicit product graph of an RSM without box-labelled transitions.
+struct ProdGraph {
+    uint32_t n, nQ;
+    const uint32_t *goff, *gidx;   // predecessors per label (columns)
+    const uint32_t *soff, *sidx;   // successors per label (rows)
+    const uint32_t *in_off, *out_off;
+    const InTrans *in_tr;          // per target state: (source state, label)
+    const InTrans *out_tr;         // per source state: (target state in .src, label)
+};
+
+// condense.hip
+hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_pivot(const ProdGraph &g, const uint8_t *alive, unsigned long long *best, hipStream_t s);
+hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *mark, uint32_t level, int backward,
+                        unsigned long long *ctr, hipStream_t s);
+hipError_t launch_set_u32(uint32_t *a, uint32_t i, uint32_t v, hipStream_t s);
+hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw, uint32_t pivot,
+                              uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_color_init(uint32_t N, const uint8_t *alive, uint32_t *color, uint8_t *found, hipStream_t s);
+hipError_t launch_color_prop(const ProdGraph &g, const uint8_t *alive, uint32_t *color, unsigned long long *ctr,
+                             hipStream_t s);
+hipError_t launch_color_roots(uint32_t N, const uint8_t *alive, const uint32_t *color, uint8_t *found, uint32_t *scc,
+                              hipStream_t s);
+hipError_t launch_color_back(const ProdGraph &g, const uint8_t *alive, const uint32_t *color, uint8_t *found,
+                             uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found, unsigned long long *ctr,
+                               hipStream_t s);
+hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *size, uint32_t *indeg,
+                             hipStream_t s);
+hipError_t launch_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts, const uint32_t *scc,
+                            uint64_t *R, hipStream_t s);
+hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *indeg, uint32_t *lev,
+                             unsigned long long *ctr, hipStream_t s);
+hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint32_t *size,
+                             uint32_t *indeg, uint32_t *lev, uint64_t *R, uint32_t L,
+                             const unsigned long long *ctr_prev, unsigned long long *ctr_next,
+                             unsigned long long *ctr_clear, hipStream_t s);
+hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc, uint64_t *T, hipStream_t s);
 
 // Fused small-graph fixpoint: one workgroup runs a whole query.
 struct FusedQuery {

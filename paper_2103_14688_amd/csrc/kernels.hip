@@ -295,7 +295,10 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     bool any = false;
     for (uint32_t k = lane; k < a.Pn; k += kWave) {
         uint64_t acc = 0;
-        for (uint32_t i = fb; i < fe; ++i) acc |= a.T[((uint64_t)a.fin[i] * a.n + v) * a.P + k];
+        for (uint32_t i = fb; i < fe; ++i) {
+            const uint64_t node = (uint64_t)a.fin[i] * a.n + v;
+            acc |= a.T[(a.row_map ? (uint64_t)a.row_map[node] : node) * a.P + k];
+        }
         const uint64_t old = nt[k];
         const uint64_t nw = acc & ~old;
         if (nw) {
@@ -483,7 +486,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
     wb.T = Q.T; wb.NT = Q.NT; wb.dNT = Q.dNT; wb.dnt_act = Q.dnt_act; wb.rank = Q.rank;
-    wb.ctr = nullptr; wb.slot_base = 0;
+    wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     uint32_t it = 0;

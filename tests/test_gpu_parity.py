@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 STRATS = [cfpq.STRATEGY_LEVELS, cfpq.STRATEGY_FUSED]
+RPQ_STRATS = [cfpq.STRATEGY_LEVELS, cfpq.STRATEGY_CONDENSED]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -118,11 +119,12 @@ def test_brackets_er256_strategies_same_iterations():
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("n,tile", [(2000, 0), (2000, 1), (2000, 7), (4100, 16), (129, 0), (65, 1)])
 @pytest.mark.parametrize("minimize", [True, False])
-def test_rpq_powerlaw(n, tile, minimize):
+@pytest.mark.parametrize("strategy", RPQ_STRATS)
+def test_rpq_powerlaw(n, tile, minimize, strategy):
     g = synth.powerlaw(n, seed=synth.BASE_SEED + 2 + n)
     want = H.oracle_regex(g, synth.RPQ_C2)
     R = rsm_mod.from_regex(synth.RPQ_C2, g.labels, minimize=minimize)
-    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, keep_blocks=True)
+    _, _, res = run(g, R, strategy=strategy, tile_words=tile, keep_blocks=True)
     check_box(res, want, g.n)
     it, deltas, _ = res.stats()
     # a regular query has one productive iteration (Sec. 3.1.2)
@@ -251,11 +253,12 @@ def test_batch_alone_vs_mix():
 # ---------------------------------------------------------------------------
 # full bench size: sampled source rows against the oracle's per-source BFS
 # ---------------------------------------------------------------------------
-def test_rpq_bench_size_sampled_rows():
+@pytest.mark.parametrize("strategy", RPQ_STRATS)
+def test_rpq_bench_size_sampled_rows(strategy):
     import oracle
     g = synth.powerlaw(100000, seed=synth.BASE_SEED + 2)
     R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
-    graph, q, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS)
+    graph, q, res = run(g, R, strategy=strategy)
     bm = res.bitmap(0)
     assert H.padding_clear(bm, g.n)
     rng = np.random.default_rng(11)
@@ -267,3 +270,62 @@ def test_rpq_bench_size_sampled_rows():
     it, deltas, _ = res.stats()
     total = int(np.unpackbits(bm.view(np.uint8)).sum())
     assert res.count(0) == total == deltas[0] and it == 2
+
+
+# ---------------------------------------------------------------------------
+# condensed closure (components of the product graph) on regular queries
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(16))
+def test_condensed_random_regex(seed):
+    rng = np.random.default_rng(7000 + seed)
+    labels = [f"l{i}" for i in range(5)]
+    n = int(rng.integers(2, 3000))
+    g = synth.powerlaw(n, labels=tuple(labels), mean_deg=float(rng.uniform(0.5, 5)), seed=seed)
+    text = synth.random_regex(rng, [str(x) for x in rng.choice(labels, size=4, replace=False)])
+    want = H.oracle_regex(g, text)
+    R = rsm_mod.from_regex(text, g.labels, minimize=bool(seed % 2))
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_CONDENSED, keep_blocks=True)
+    check_box(res, want, g.n)
+    it, deltas, _ = res.stats()
+    assert it == 2 and deltas[1] == 0
+
+
+@pytest.mark.parametrize("text", ["a*", "(a | b)+", "a b a", "eps", "(a b)* | b"])
+def test_condensed_cycles_and_chains(text):
+    # a long chain (deep condensation), a ring (one big component), self-loops
+    chain = [(i, "a" if i % 3 else "b", i + 1) for i in range(4999)]
+    ring = [(5000 + i, "a", 5000 + (i + 1) % 700) for i in range(700)]
+    loops = [(i, "b", i) for i in range(0, 5700, 97)]
+    g = synth.make_graph(5700, chain + ring + loops, ["a", "b"])
+    want = H.oracle_regex(g, text)
+    R = rsm_mod.from_regex(text, g.labels)
+    for strategy in RPQ_STRATS:
+        _, _, res = run(g, R, strategy=strategy)
+        check_box(res, want, g.n)
+
+
+def test_condensed_rejects_grammars():
+    g = synth.chain("aabb")
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(rsm_mod.from_grammar(synth.BRACKETS, g.labels))
+    with pytest.raises(cfpq.CfpqError) as e:
+        cfpq.query(graph, q, strategy=cfpq.STRATEGY_CONDENSED)
+    assert e.value.status == cfpq.ERR_INVALID
+
+
+def test_condensed_and_levels_agree_with_witnesses():
+    g = synth.powerlaw(1500, seed=21)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
+    _, _, a = run(g, R, strategy=cfpq.STRATEGY_CONDENSED, keep_rank=True)
+    _, _, b = run(g, R, strategy=cfpq.STRATEGY_LEVELS)
+    assert np.array_equal(a.bitmap(0), b.bitmap(0))
+    assert a.stats()[:2] == b.stats()[:2]
+    pairs = a.pairs(0)
+    import re
+    pat = re.compile("(a|b)*cd*")
+    edges = set(zip(g.src.tolist(), g.lbl.tolist(), g.dst.tolist()))
+    for u, v in pairs[:: max(1, len(pairs) // 20)].tolist():
+        path = a.extract_path(u, v)
+        assert path[0][0] == u and path[-1][2] == v
+        assert all((int(x), int(l), int(y)) in edges for x, l, y in path)
+        assert pat.fullmatch("".join(g.labels[int(l)] for _, l, _ in path))
