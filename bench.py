@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=400)
     ap.add_argument("--serve-nmax", type=int, default=20000)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--workload", choices=["rpq", "brackets", "samegen", "alias"], default="rpq",
+                    help="rpq (default, the headline) or one of the other measured workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (reference kernel for the "
                          "FETCH_SIZE/WRITE_SIZE scale factor) and exit")
@@ -71,6 +73,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload != "rpq":
+        print(json.dumps(other_workload(args)), flush=True)
+        return
     g = synth.powerlaw(args.n, seed=synth.BASE_SEED + 2)
     R = rsm.from_regex(synth.RPQ_C2, g.labels)
     graph = cfpq.Graph.from_synth(g)
@@ -164,6 +169,91 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = [fn() for _ in range(steps)]
+    torch.cuda.synchronize()
+    return out, (time.perf_counter() - t0) / steps
+
+
+def other_workload(args):
+    """The other measured workloads (one JSON line each):
+    brackets -- S -> a S b | a b on directed Erdos-Renyi n = 256, p = 2/n per
+                label: the latency-bound plain query (levels and fused
+                strategies) and 1024 such queries (seeds) in one fused launch;
+    samegen  -- same-generation grammar G1 on a hierarchy (tree with Poisson(4)
+                branching, 20% type edges, inverse labels), n = args.n;
+    alias    -- memory-alias grammar on a clustered program-like graph, n = args.n."""
+    import numpy as np
+
+    import synth
+    from paper_2103_14688_amd import cfpq, rsm
+
+    out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "data": "synthetic", "dtype": "u64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None}
+    if args.workload == "brackets":
+        g = synth.erdos_renyi(256, seed=synth.BASE_SEED + 1)
+        graph = cfpq.Graph.from_synth(g)
+        q = cfpq.Query(rsm.from_grammar(synth.BRACKETS, g.labels))
+        res = {}
+        for name, st in (("levels", cfpq.STRATEGY_LEVELS), ("fused", cfpq.STRATEGY_FUSED)):
+            rs, dt = timed(lambda: cfpq.query(graph, q, strategy=st), args.steps, args.warmup)
+            it, deltas, ms = rs[-1].stats()
+            res[name] = {"ms_per_query_wall": dt * 1e3, "fixpoint_ms": ms, "iterations": it,
+                         "us_per_iteration": ms * 1e3 / it, "pairs": rs[-1].count(0)}
+        # batch: 1024 graphs (seeds), one persistent fused launch
+        gs = [synth.erdos_renyi(256, seed=synth.BASE_SEED + 1000 + i) for i in range(1024)]
+        hs = [cfpq.Graph.from_synth(x) for x in gs]
+        qs = [q] * len(hs)
+        rs, dt = timed(lambda: cfpq.query_batch(hs, qs), max(1, args.steps // 2), 1)
+        pairs = sum(r.count(0) for r in rs[-1])
+        res["batched_1024"] = {"ms_per_batch_wall": dt * 1e3, "queries_per_s": 1024 / dt,
+                               "pairs_per_s": pairs / dt, "pairs": pairs}
+        out.update({"metric": "reachable pairs/s, balanced brackets (plain vs fused vs batched)",
+                    "value": res["batched_1024"]["pairs_per_s"], "unit": "pairs/s",
+                    "ms_per_step": res["fused"]["ms_per_query_wall"],
+                    "config": {"workload": "S -> a S b | a b on directed Erdos-Renyi n=256, p=2/n per label",
+                               **res}})
+        return out
+    if args.workload == "samegen":
+        g, depth = synth.hierarchy(args.n, seed=synth.BASE_SEED + 3)
+        text = synth.SAME_GEN_G1
+    else:
+        g = synth.clustered(args.n, seed=synth.BASE_SEED + 4)
+        text = synth.MEM_ALIAS
+    R = rsm.from_grammar(text, g.labels)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    rs, dt = timed(lambda: cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=args.tile_words,
+                                      profile=True), args.steps, args.warmup)
+    r = rs[-1]
+    it, deltas, ms = r.stats()
+    pairs = r.count(0)
+    lv = r.profile(cfpq.KERNEL_LEVEL)
+    sd = r.profile(cfpq.KERNEL_SEED)
+    wb = r.profile(cfpq.KERNEL_WRITEBACK)
+    achieved = lv[2] / (lv[1] * 1e-3) / 1e9 if lv[1] else 0.0
+    out.update({
+        "metric": f"reachable pairs/s ({args.workload})", "value": pairs / dt, "unit": "pairs/s",
+        "ms_per_step": dt * 1e3,
+        "config": {"workload": (f"same-generation G1 on hierarchy n={g.n}" if args.workload == "samegen"
+                                else f"memory alias MA on clustered graph n={g.n}"),
+                   "n": g.n, "edges": int(len(g.src)), "rsm_states": int(R.n_states), "pairs": pairs,
+                   "all_box_pairs": {b: r.count(b) for b in R.box_names}, "iterations": it,
+                   "fixpoint_ms": ms, "deltas_head": deltas[:12],
+                   "level": {"launches": lv[0], "ms": lv[1], "GB": lv[2] / 1e9},
+                   "seed": {"launches": sd[0], "ms": sd[1]}, "writeback": {"launches": wb[0], "ms": wb[1]}},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gather<false> (closure frontier level)"},
+    })
+    return out
 
 
 def measure_serving(args):

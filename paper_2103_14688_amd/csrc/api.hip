@@ -315,6 +315,7 @@ struct Plan {
     std::vector<uint32_t> fin_off, fin;
     std::vector<uint32_t> eps_boxes;  // boxes whose start is final
     std::vector<uint8_t> nullable, box_used;
+    std::vector<uint32_t> is_start;      // per state: initial state of its box
 };
 
 Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
@@ -339,6 +340,8 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     for (size_t i = 0; i < r.t_src.size(); ++i) p.out_tr[ofill[r.t_src[i]]++] = InTrans{r.t_dst[i], r.t_sym[i]};
     for (size_t i = 0; i < r.t_sym.size(); ++i) p.has_calls |= r.t_sym[i] >= r.n_terms;
     p.starts = r.box_start;
+    p.is_start.assign(p.nQ, 0);
+    for (uint32_t b = 0; b < p.nB; ++b) p.is_start[r.box_start[b]] = 1;
     p.fin_off.assign(p.nB + 1, 0);
     for (uint32_t q = 0; q < p.nQ; ++q)
         if (r.is_final[q]) p.fin_off[r.state_box[q] + 1]++;
@@ -363,7 +366,7 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
 struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
-             *eps = nullptr, *out_off = nullptr;
+             *eps = nullptr, *out_off = nullptr, *is_start = nullptr;
     InTrans *in_tr = nullptr, *out_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
@@ -386,6 +389,7 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     size_t o_used = put(p.box_used.data(), p.box_used.size());
     size_t o_out_off = put(p.out_off.data(), p.out_off.size() * 4);
     size_t o_out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
+    size_t o_is_start = put(p.is_start.data(), p.is_start.size() * 4);
     if (!t.buf.alloc(al, host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
     HIP_TRY(hipMemcpyAsync(t.buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
     uint8_t *b = t.buf.as<uint8_t>();
@@ -399,6 +403,7 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     t.box_used = b + o_used;
     t.out_off = (uint32_t *)(b + o_out_off);
     t.out_tr = (InTrans *)(b + o_out_tr);
+    t.is_start = (uint32_t *)(b + o_is_start);
     // the host vector dies with this frame: wait for the copy
     HIP_TRY(hipStreamSynchronize(s));
     return CFPQ_OK;
@@ -685,6 +690,17 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     Plan p = make_plan(g, r);
     if (p.has_calls) return fail(CFPQ_ERR_INVALID, "condensed strategy needs an RSM without box-labelled transitions");
     if ((uint64_t)p.nQ * p.n >= 0xFFFFFFFFull) return fail(CFPQ_ERR_LIMIT, "product graph exceeds 2^32-1 nodes");
+    // state flags: box start; only final state of its box (then single-member
+    // rows of that state are the answer rows themselves); box id
+    {
+        const bool can_alias = p.eps_boxes.empty() && !o.keep_blocks && !o.keep_rank;
+        for (uint32_t q = 0; q < p.nQ; ++q) {
+            const uint32_t b = r.state_box[q];
+            const bool only_final = r.is_final[q] && p.fin_off[b + 1] - p.fin_off[b] == 1;
+            p.is_start[q] = (p.is_start[q] ? kStartState : 0) | ((can_alias && only_final) ? kAliasFinal : 0) |
+                            (b << kFlagBoxShift);
+        }
+    }
     Tables tb;
     cfpq_status st = upload_tables(p, al, s, tb);
     if (st != CFPQ_OK) return st;
@@ -695,19 +711,23 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     const uint64_t Nu = ((uint64_t)N + 1) / 2 * 2;         // u32 arrays start on 8-byte boundaries
     constexpr uint32_t kCtr = 8192;
     if ((uint64_t)nB * kSlotWords > kCtr) return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
+    const uint32_t nch = (Pn + kCondChunkWords - 1) / kCondChunkWords;
+    const uint64_t nzb = ((uint64_t)N * nch + 63) / 64 * 64;   // non-empty chunk flags
 
     DevBuf T, dNT, dnt_act, u32s, u8s, ctr;
-    if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
-        !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) || !u32s.alloc(al, Nu * 4 * 6 + 64, s) ||
-        !u8s.alloc(al, 2 * N64 + 64, s) || !ctr.alloc(al, (uint64_t)2 * kCtr * 8, s))
+    const bool nullable = !p.eps_boxes.empty();
+    if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, nullable ? bw * 8 : 8, s) ||
+        !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) || !u32s.alloc(al, Nu * 4 * (8 + kStripes) + 64, s) ||
+        !u8s.alloc(al, 2 * N64 + nzb + 64, s) || !ctr.alloc(al, (uint64_t)2 * kCtr * 8, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (condensed query)");
     if (o.keep_rank) {
         if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
         HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)nB * n * n, s));
     }
     uint32_t *scc = u32s.as<uint32_t>(), *fw = scc + Nu, *bwm = fw + Nu, *color = bwm + Nu, *size = color + Nu,
-             *indeg = size + Nu, *lev = fw;  // lev reuses fw after the search
-    uint8_t *alive = u8s.as<uint8_t>(), *found = alive + N64;
+             *pending = size + Nu, *qa = pending + Nu, *qb = qa + Nu, *stripe = qb + Nu,
+             *lev = fw;  // lev reuses fw after the search
+    uint8_t *alive = u8s.as<uint8_t>(), *found = alive + N64, *nzf = found + N64;
     unsigned long long *cc = ctr.as<unsigned long long>();
     unsigned long long *lc = cc + kCtr;   // ring of per-level component counts
     ProdGraph pg{};
@@ -743,34 +763,52 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         HIP_TRY(hipStreamSynchronize(s));
         return CFPQ_OK;
     };
-    // run launch(slot) until a launch counts zero, up to max_rounds
-    auto until_zero = [&](auto launch, uint32_t max_rounds) -> cfpq_status {
-        for (uint32_t i = 0; i < max_rounds; ++i) {
-            cfpq_status st2 = next_slot(1);
+    // run launch(i, prev, cur) as a chain until a launch counts zero: chunks of
+    // launches go out back to back, each exits at once when its predecessor
+    // counted zero, and the host reads the chunk's counters once
+    auto chain = [&](auto launch, uint32_t chunk) -> cfpq_status {
+        const unsigned long long *prev = nullptr;
+        for (uint32_t i = 0;;) {
+            if (slot + chunk >= kCtr) {
+                // clearing the counters loses prev; the launch it belongs to
+                // counted nonzero (else the chain had ended), so run on
+                HIP_TRY(launch_fill((uint64_t *)cc, kCtr, 0, s));
+                slot = 0;
+                prev = nullptr;
+            }
+            const uint32_t first = slot;
+            for (uint32_t j = 0; j < chunk; ++j, ++i) {
+                HIP_TRY(launch(i, prev, cc + slot));
+                prev = cc + slot++;
+            }
+            cfpq_status st2 = read(first, chunk);
             if (st2 != CFPQ_OK) return st2;
-            HIP_TRY(launch(cc + slot));
-            if ((st2 = read(slot, 1)) != CFPQ_OK) return st2;
-            ++slot;
-            if (pc.h[0] == 0) return CFPQ_OK;
+            for (uint32_t j = 0; j < chunk; ++j)
+                if (pc.h[j] == 0) return CFPQ_OK;
+            chunk = std::min<uint32_t>(chunk * 2, 256);
         }
-        return CFPQ_OK;
     };
 
     HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_fill(d_u64(T), qw, 0, s));
-    HIP_TRY(launch_fill(d_u64(res.NT), bw, 0, s));
-    HIP_TRY(launch_fill(d_u64(dNT), bw, 0, s));
-    HIP_TRY(launch_fill(d_u64(dnt_act), (uint64_t)nB * Pn, 0, s));
+    // M2^N is empty unless a box is nullable; then it needs the epsilon loops
+    const bool fresh = p.eps_boxes.empty();
+    if (!fresh) HIP_TRY(launch_fill(d_u64(res.NT), bw, 0, s));
     HIP_TRY(launch_fill((uint64_t *)cc, 2 * kCtr, 0, s));
-    HIP_TRY(launch_fill((uint64_t *)u32s.p, (Nu * 4 * 6 + 64) / 8, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)u32s.p, (Nu * 4 * (8 + kStripes) + 64) / 8, 0, s));
     HIP_TRY(launch_fill((uint64_t *)alive, N64 / 8, 0x0101010101010101ull, s));  // every node live
-    HIP_TRY(launch_fill((uint64_t *)found, N64 / 8 + 8, 0, s));
-    HIP_TRY(launch_eps(d_u64(res.NT), d_u64(dNT), d_u64(dnt_act), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
-                       Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+    HIP_TRY(launch_fill((uint64_t *)found, (N64 + nzb) / 8 + 8, 0, s));   // found, non-empty flags := 0
+    if (!fresh) {
+        HIP_TRY(launch_fill(d_u64(dNT), bw, 0, s));
+        HIP_TRY(launch_fill(d_u64(dnt_act), (uint64_t)nB * Pn, 0, s));
+        HIP_TRY(launch_eps(d_u64(res.NT), d_u64(dNT), d_u64(dnt_act), o.keep_rank ? res.rank.as<uint8_t>() : nullptr,
+                           n, P, Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+    }
 
     // ---- strongly connected components of the product graph
     // trimming: nodes with no live predecessor or successor
-    st = until_zero([&](unsigned long long *c) { return launch_trim(pg, alive, scc, c, s); }, 64);
+    st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
+        return launch_trim(pg, alive, scc, pv, c, s);
+    }, 8);
     if (st != CFPQ_OK) return st;
     // the component of a high-degree pivot: forward AND backward reachable
     {
@@ -782,16 +820,10 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             const uint32_t pivot = (uint32_t)(pc.h[0] & 0xFFFFFFFFull);
             HIP_TRY(launch_set_u32(fw, pivot, 1, s));
             HIP_TRY(launch_set_u32(bwm, pivot, 1, s));
-            for (int dir = 0; dir < 2; ++dir) {
-                uint32_t *mark = dir ? bwm : fw;
-                for (uint32_t level = 1;; ++level) {
-                    if ((st = next_slot(1)) != CFPQ_OK) return st;
-                    HIP_TRY(launch_reach(pg, alive, mark, level, dir, cc + slot, s));
-                    if ((st = read(slot, 1)) != CFPQ_OK) return st;
-                    ++slot;
-                    if (pc.h[0] == 0) break;
-                }
-            }
+            st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
+                return launch_reach(pg, alive, fw, bwm, pv, c, s);
+            }, 8);
+            if (st != CFPQ_OK) return st;
             if ((st = next_slot(1)) != CFPQ_OK) return st;
             HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, pivot, scc, cc + slot++, s));
         }
@@ -804,24 +836,31 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         if ((st = read(rem_slot, 1)) != CFPQ_OK) return st;
         if (pc.h[0] == 0) break;
         HIP_TRY(launch_color_init(N, alive, color, found, s));
-        st = until_zero([&](unsigned long long *c) { return launch_color_prop(pg, alive, color, c, s); }, 0xFFFFFFFFu);
+        st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
+            return launch_color_prop(pg, alive, color, pv, c, s);
+        }, 8);
         if (st != CFPQ_OK) return st;
         HIP_TRY(launch_color_roots(N, alive, color, found, scc, s));
-        st = until_zero([&](unsigned long long *c) { return launch_color_back(pg, alive, color, found, scc, c, s); },
-                        0xFFFFFFFFu);
+        st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
+            return launch_color_back(pg, alive, color, found, scc, pv, c, s);
+        }, 8);
         if (st != CFPQ_OK) return st;
     }
     HIP_TRY(hipEventRecord(ev[1], s));
 
     // ---- condensation, one topological level per launch
     HIP_TRY(launch_fill((uint64_t *)fw, (Nu * 4 * 2) / 8, 0, s));  // lev (reuses fw/bw) := 0
-    HIP_TRY(launch_cond_count(pg, scc, size, indeg, s));
-    HIP_TRY(launch_cond_seed(n, P, tb.starts, nB, scc, d_u64(T), s));
+    HIP_TRY(launch_cond_count(pg, scc, size, stripe, s));
+    HIP_TRY(launch_cond_seed(n, P, Pn, nQ, tb.starts, nB, scc, size, d_u64(T), nzf, s));
     // level L's component count lives in lc[L % kCtr]; the launch for level L
     // clears lc[(L + 2) % kCtr] before level L + 1 writes it
-    HIP_TRY(launch_cond_roots(N, scc, indeg, lev, lc + 0, s));
+    HIP_TRY(launch_cond_roots(N, scc, stripe, pending, lev, lc + 0, s));
     uint32_t L = 0, hint = 32;
     uint64_t comps = 0;
+    // answer pairs counted by the closure: kWave stripes per box
+    if ((uint64_t)nB * (kWave + kSlotWords) > kCtr) return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
+    unsigned long long *box_pairs = cc;   // the misc counters are not used from here on
+    HIP_TRY(launch_fill((uint64_t *)box_pairs, (uint64_t)nB * kWave, 0, s));
     std::vector<hipEvent_t> lev_ev;   // profiling: an event before each level launch, one after the chunk
     struct PoolGuard {
         std::vector<hipEvent_t> *v;
@@ -840,8 +879,9 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         for (uint32_t j = 0; j < k; ++j) {
             const uint32_t l = L + j;
             if (prof) HIP_TRY(hipEventRecord(lev_ev[j], s));
-            HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, indeg, lev, d_u64(T), l, lc + l % kCtr,
-                                      lc + (l + 1) % kCtr, lc + (l + 2) % kCtr, s));
+            HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, stripe, pending, lev, d_u64(T), d_u64(res.NT), nzf,
+                                      tb.is_start, l, lc + l % kCtr, lc + (l + 1) % kCtr, lc + (l + 2) % kCtr,
+                                      box_pairs, s));
         }
         if (prof) HIP_TRY(hipEventRecord(lev_ev[k], s));
         HIP_TRY(hipMemcpyAsync(pc.h, lc, (size_t)kCtr * 8, hipMemcpyDeviceToHost, s));
@@ -870,21 +910,27 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         if (L > 0xFFFFFFFFu - 2048) return fail(CFPQ_ERR_LIMIT, "condensation too deep");
     }
     HIP_TRY(hipEventRecord(ev[2], s));
-    // ---- write-back through the component map
-    HIP_TRY(launch_fill(d_u64(dnt_act), (uint64_t)nB * Pn, 0, s));
-    HIP_TRY(launch_fill((uint64_t *)cc, (uint64_t)nB * kSlotWords, 0, s));
+    // ---- write-back through the component map for the answer rows the
+    // closure did not write itself; nothing reads the deltas of a query
+    // without box-labelled transitions, so none are kept
+    unsigned long long *wb_ctr = cc + (uint64_t)nB * kWave;
+    HIP_TRY(launch_fill((uint64_t *)wb_ctr, (uint64_t)nB * kSlotWords, 0, s));
     WritebackArgs w{};
     w.n = n; w.P = P; w.Pn = Pn; w.nB = nB; w.fin_off = tb.fin_off; w.fin = tb.fin;
-    w.T = d_u64(T); w.NT = d_u64(res.NT); w.dNT = d_u64(dNT); w.dnt_act = d_u64(dnt_act);
+    w.T = d_u64(T); w.NT = d_u64(res.NT); w.dNT = nullptr; w.dnt_act = nullptr; w.fresh = fresh;
     w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
-    w.iter = 1; w.ctr = cc; w.slot_base = 0; w.row_map = scc;
+    w.iter = 1; w.ctr = wb_ctr; w.slot_base = 0; w.row_map = scc; w.row_nz = nzf;
+    w.state_flags = tb.is_start; w.multi = size;
     HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
-    if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, d_u64(T), s));
+    if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, nzf, d_u64(T), s));
     HIP_TRY(hipEventRecord(ev[3], s));
-    HIP_TRY(hipMemcpyAsync(pc.h, cc, (size_t)nB * kSlotWords * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(pc.h, cc, ((size_t)nB * kWave + (size_t)nB * kSlotWords) * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     uint64_t delta = 0;
-    for (uint32_t b = 0; b < nB; ++b) delta += pc.h[(size_t)b * kSlotWords];
+    for (uint32_t b = 0; b < nB; ++b) {
+        for (uint32_t j = 0; j < kWave; ++j) delta += pc.h[(size_t)b * kWave + j];
+        delta += pc.h[(size_t)nB * kWave + (size_t)b * kSlotWords];
+    }
     // a second iteration would seed from box-labelled transitions only: none
     res.deltas.assign({delta, 0});
     res.iterations = 2;

@@ -75,7 +75,11 @@ struct WritebackArgs {
     unsigned long long *ctr;
     uint32_t slot_base;            // new edges of box N counted at slot_base + N
     const uint32_t *row_map;       // optional: T row of product node (f, v) is row_map[f*n+v]
-};
+    int fresh;                     // M2^N is known empty: write it without reading
+    const uint8_t *row_nz;         // optional: per (T row, 512-word chunk) flag; 0 = the chunk is all zero
+    const uint32_t *state_flags;   // optional (with multi): rows of single-member components of a
+    const uint32_t *multi;         //   kAliasFinal state are already in NT; such rows are skipped
+};                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip
 hipError_t launch_fill(uint64_t *p, uint64_t words, uint64_t value, hipStream_t s);
@@ -105,33 +109,47 @@ struct ProdGraph {
 };
 
 // condense.hip
-hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
+                       unsigned long long *ctr, hipStream_t s);
 hipError_t launch_pivot(const ProdGraph &g, const uint8_t *alive, unsigned long long *best, hipStream_t s);
-hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *mark, uint32_t level, int backward,
-                        unsigned long long *ctr, hipStream_t s);
+hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
+                        const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_set_u32(uint32_t *a, uint32_t i, uint32_t v, hipStream_t s);
+hipError_t launch_set_u64(unsigned long long *a, unsigned long long v, hipStream_t s);
+hipError_t launch_push(const ProdGraph &g, const uint8_t *alive, uint32_t *mark, int backward, const uint32_t *fin,
+                       const unsigned long long *n_in, uint32_t *fout, unsigned long long *n_out, uint32_t grid,
+                       hipStream_t s);
+constexpr uint32_t kStripes = 16;           // in-degree counters per component
+// per-state flags of the condensed strategy: bit 0 box start, bit 1 the only
+// final state of its box (its single-member rows alias the answer), box id
+// from bit 2 up
+constexpr uint32_t kStartState = 1, kAliasFinal = 2, kFlagBoxShift = 2;
 hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw, uint32_t pivot,
                               uint32_t *scc, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_init(uint32_t N, const uint8_t *alive, uint32_t *color, uint8_t *found, hipStream_t s);
-hipError_t launch_color_prop(const ProdGraph &g, const uint8_t *alive, uint32_t *color, unsigned long long *ctr,
-                             hipStream_t s);
+hipError_t launch_color_prop(const ProdGraph &g, const uint8_t *alive, uint32_t *color,
+                             const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_roots(uint32_t N, const uint8_t *alive, const uint32_t *color, uint8_t *found, uint32_t *scc,
                               hipStream_t s);
 hipError_t launch_color_back(const ProdGraph &g, const uint8_t *alive, const uint32_t *color, uint8_t *found,
-                             uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+                             uint32_t *scc, const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found, unsigned long long *ctr,
                                hipStream_t s);
-hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *size, uint32_t *indeg,
+hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *size, uint32_t *stripe,
                              hipStream_t s);
-hipError_t launch_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts, const uint32_t *scc,
-                            uint64_t *R, hipStream_t s);
-hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *indeg, uint32_t *lev,
-                             unsigned long long *ctr, hipStream_t s);
-hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint32_t *size,
-                             uint32_t *indeg, uint32_t *lev, uint64_t *R, uint32_t L,
-                             const unsigned long long *ctr_prev, unsigned long long *ctr_next,
-                             unsigned long long *ctr_clear, hipStream_t s);
-hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc, uint64_t *T, hipStream_t s);
+hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, const uint32_t *starts,
+                            uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
+                            hipStream_t s);
+hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *stripe, uint32_t *pending,
+                             uint32_t *lev, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint32_t *multi,
+                             uint32_t *indeg, uint32_t *pending, uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
+                             const uint32_t *flags, uint32_t L, const unsigned long long *ctr_prev,
+                             unsigned long long *ctr_next, unsigned long long *ctr_clear, unsigned long long *box_pairs,
+                             hipStream_t s);
+hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint8_t *nz, uint64_t *T,
+                              hipStream_t s);
+constexpr uint32_t kCondChunkWords = 512;   // chunk of a component row with its own non-empty flag
 
 // Fused small-graph fixpoint: one workgroup runs a whole query.
 struct FusedQuery {

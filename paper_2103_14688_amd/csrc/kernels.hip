@@ -291,18 +291,22 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     const int lane = __lane_id();
     const uint32_t fb = a.fin_off[N], fe = a.fin_off[N + 1];
     uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
-    uint64_t *dnt = a.dNT + ((uint64_t)N * a.n + v) * a.P;
+    uint64_t *dnt = a.dNT ? a.dNT + ((uint64_t)N * a.n + v) * a.P : nullptr;
     bool any = false;
     for (uint32_t k = lane; k < a.Pn; k += kWave) {
         uint64_t acc = 0;
         for (uint32_t i = fb; i < fe; ++i) {
             const uint64_t node = (uint64_t)a.fin[i] * a.n + v;
-            acc |= a.T[(a.row_map ? (uint64_t)a.row_map[node] : node) * a.P + k];
+            const uint64_t row = a.row_map ? (uint64_t)a.row_map[node] : node;
+            if (a.row_nz && !a.row_nz[row * ((a.Pn + kCondChunkWords - 1) / kCondChunkWords) + k / kCondChunkWords])
+                continue;  // chunk never written: all zero
+            acc |= a.T[row * a.P + k];
         }
-        const uint64_t old = nt[k];
+        const uint64_t old = a.fresh ? 0ull : nt[k];
         const uint64_t nw = acc & ~old;
+        if (a.fresh) nt[k] = nw;  // M2^N was empty: write without reading
         if (nw) {
-            nt[k] = old | nw;
+            if (!a.fresh) nt[k] = old | nw;
             any = true;
             cnt_box += (unsigned long long)__popcll(nw);
             if (a.rank) {
@@ -314,7 +318,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
                 }
             }
         }
-        dnt[k] = nw;
+        if (dnt) dnt[k] = nw;
     }
     any_row = __ballot(any) != 0;
 }
@@ -327,13 +331,24 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
     const uint64_t rows = (uint64_t)a.nB * a.n;
     for (uint64_t r = wave; r < rows; r += nwaves) {
         const uint32_t N = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
-        if (a.fin_off[N] == a.fin_off[N + 1]) continue;
+        if (a.fin_off[N] == a.fin_off[N + 1]) {
+            // a box without final states derives nothing: its relation is empty
+            if (a.fresh)
+                for (uint32_t k = lane; k < a.Pn; k += kWave) a.NT[((uint64_t)N * a.n + v) * a.P + k] = 0;
+            continue;
+        }
+        if (a.state_flags) {
+            const uint32_t f = a.fin[a.fin_off[N]];
+            if ((a.state_flags[f] & kAliasFinal) && a.multi[a.row_map[(uint64_t)f * a.n + v]] == 0)
+                continue;  // written (and counted) by the closure itself
+        }
         unsigned long long c = 0;
         bool any = false;
         writeback_row(a, N, v, c, any);
         c = wave_sum(c);
         if (lane == 0 && any) {
-            atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
+            if (a.dnt_act)
+                atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
             atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
         }
     }
@@ -486,7 +501,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
     wb.T = Q.T; wb.NT = Q.NT; wb.dNT = Q.dNT; wb.dnt_act = Q.dnt_act; wb.rank = Q.rank;
-    wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr;
+    wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr; wb.fresh = 0; wb.row_nz = nullptr;
+    wb.state_flags = nullptr; wb.multi = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     uint32_t it = 0;

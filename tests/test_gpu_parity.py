@@ -290,18 +290,19 @@ def test_condensed_random_regex(seed):
     assert it == 2 and deltas[1] == 0
 
 
-@pytest.mark.parametrize("text", ["a*", "(a | b)+", "a b a", "eps", "(a b)* | b"])
+@pytest.mark.parametrize("text", ["a*", "(a | b)+", "a b a", "eps", "(a b)* | b", "zz", "a zz"])
 def test_condensed_cycles_and_chains(text):
     # a long chain (deep condensation), a ring (one big component), self-loops
     chain = [(i, "a" if i % 3 else "b", i + 1) for i in range(4999)]
-    ring = [(5000 + i, "a", 5000 + (i + 1) % 700) for i in range(700)]
-    loops = [(i, "b", i) for i in range(0, 5700, 97)]
-    g = synth.make_graph(5700, chain + ring + loops, ["a", "b"])
+    ring = [(5000 + i, "a", 5000 + (i + 1) % 9500) for i in range(9500)]   # one component, 9500 hops round
+    loops = [(i, "b", i) for i in range(0, 14500, 97)]
+    g = synth.make_graph(14500, chain + ring + loops, ["a", "b"])
     want = H.oracle_regex(g, text)
     R = rsm_mod.from_regex(text, g.labels)
     for strategy in RPQ_STRATS:
-        _, _, res = run(g, R, strategy=strategy)
-        check_box(res, want, g.n)
+        for kw in ({}, {"keep_blocks": True}):
+            _, _, res = run(g, R, strategy=strategy, **kw)
+            check_box(res, want, g.n)
 
 
 def test_condensed_rejects_grammars():
