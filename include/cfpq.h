@@ -143,6 +143,9 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                it; required by cfpq_extract_path (n <= 16384).
  *   keep_blocks: keep the closure blocks, required by cfpq_result_block.
  *   tile_words : source-tile width in 64-bit words (0 = automatic).
+ *   dense_nt   : nonzero: never use the sparse (ELL + LDS accumulator)
+ *                nonterminal product in the Kronecker seed; every selector
+ *                bit ORs its whole source row (for comparison and tests).
  *   profile    : record HIP events around every launch of the levels
  *                strategy (see cfpq_result_profile); adds ~1 us per launch.
  *   stream     : hipStream_t for all work of the call (NULL = null stream).
@@ -159,6 +162,8 @@ typedef struct {
     uint32_t keep_blocks;
     uint32_t tile_words;
     uint32_t profile;
+    uint32_t dense_nt;
+    uint32_t reserved;
     void *stream;
     const cfpq_allocator *alloc;
 } cfpq_query_opts;

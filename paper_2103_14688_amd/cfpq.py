@@ -48,6 +48,7 @@ class Allocator(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("keep_rank", ctypes.c_uint32),
                 ("keep_blocks", ctypes.c_uint32), ("tile_words", ctypes.c_uint32), ("profile", ctypes.c_uint32),
+                ("dense_nt", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("alloc", ctypes.POINTER(Allocator))]
 
 
@@ -180,8 +181,9 @@ def cfpq_rsm_destroy(r):
 
 
 def make_opts(strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-              stream=None, alloc=None, profile=False):
-    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), stream, None)
+              stream=None, alloc=None, profile=False, dense_nt=False):
+    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(dense_nt), 0,
+                  stream, None)
     if alloc is not None:
         o.alloc = ctypes.pointer(alloc)
     return o
@@ -381,10 +383,10 @@ class Result:
 
 
 def query(graph, q, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-          stream=None, profile=False):
+          stream=None, profile=False, dense_nt=False):
     if stream is None:
         stream = current_stream()
-    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile)
+    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, dense_nt)
     return Result(cfpq_query(graph.h, q.h, o), graph, q)
 
 

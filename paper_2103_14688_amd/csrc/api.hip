@@ -316,6 +316,7 @@ struct Plan {
     std::vector<uint32_t> eps_boxes;  // boxes whose start is final
     std::vector<uint8_t> nullable, box_used;
     std::vector<uint32_t> is_start;      // per state: initial state of its box
+    std::vector<uint32_t> nt_src;        // source states of box-labelled transitions
 };
 
 Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
@@ -339,6 +340,14 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     std::vector<uint32_t> ofill(p.out_off.begin(), p.out_off.end() - 1);
     for (size_t i = 0; i < r.t_src.size(); ++i) p.out_tr[ofill[r.t_src[i]]++] = InTrans{r.t_dst[i], r.t_sym[i]};
     for (size_t i = 0; i < r.t_sym.size(); ++i) p.has_calls |= r.t_sym[i] >= r.n_terms;
+    {
+        std::vector<uint8_t> seen(p.nQ, 0);
+        for (size_t i = 0; i < r.t_sym.size(); ++i)
+            if (r.t_sym[i] >= r.n_terms && !seen[r.t_src[i]]) {
+                seen[r.t_src[i]] = 1;
+                p.nt_src.push_back(r.t_src[i]);
+            }
+    }
     p.starts = r.box_start;
     p.is_start.assign(p.nQ, 0);
     for (uint32_t b = 0; b < p.nB; ++b) p.is_start[r.box_start[b]] = 1;
@@ -366,7 +375,7 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
 struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
-             *eps = nullptr, *out_off = nullptr, *is_start = nullptr;
+             *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr;
     InTrans *in_tr = nullptr, *out_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
@@ -390,6 +399,7 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     size_t o_out_off = put(p.out_off.data(), p.out_off.size() * 4);
     size_t o_out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
     size_t o_is_start = put(p.is_start.data(), p.is_start.size() * 4);
+    size_t o_nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
     if (!t.buf.alloc(al, host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
     HIP_TRY(hipMemcpyAsync(t.buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
     uint8_t *b = t.buf.as<uint8_t>();
@@ -404,6 +414,7 @@ cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables 
     t.out_off = (uint32_t *)(b + o_out_off);
     t.out_tr = (InTrans *)(b + o_out_tr);
     t.is_start = (uint32_t *)(b + o_is_start);
+    t.nt_src = (uint32_t *)(b + o_nt_src);
     // the host vector dies with this frame: wait for the copy
     HIP_TRY(hipStreamSynchronize(s));
     return CFPQ_OK;
@@ -468,7 +479,12 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     const uint64_t aw = (uint64_t)nQ * Pn;
     const uint64_t ring_words = (uint64_t)kRingSlots * kSlotWords;
 
-    DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr;
+    DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr, ell;
+    // sparse nonterminal product in the seed: ELL lists of the source rows and
+    // an LDS row accumulator per wavefront (tiles up to kSparseMaxWords words)
+    const bool sparse_nt = !p.nt_src.empty() && G <= kSparseMaxWords && !o.dense_nt;
+    if (sparse_nt && !ell.alloc(al, (uint64_t)nQ * n * (kEll + 1) * 4, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (sparse product index)");
     if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
         !D0.alloc(al, fw * 8, s) || !D1.alloc(al, fw * 8, s) || !acts.alloc(al, 3 * aw * 8, s) ||
         !tnz.alloc(al, aw * 8, s) || !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) ||
@@ -581,6 +597,16 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             a.src = d_T; a.src_pitch = P; a.src_off = w0; a.src_act = tnz.as<uint64_t>();
             a.dn = Dbuf[0]; a.actn = act[0]; a.act_clear = nullptr;
             a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1);
+            a.extra = nullptr; a.extra_act = nullptr;
+            if (sparse_nt) {
+                // the product rows go to the other frontier buffer and the third
+                // activity bitset, both unused until the first level
+                uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
+                HIP_TRY(launch_ell_build(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt, ell_idx,
+                                         s));
+                HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dbuf[1], act[2], grid, s));
+                a.extra = Dbuf[1]; a.extra_act = act[2];
+            }
             const uint32_t seed_slot = slot;
             if ((st = prof_mark(0)) != CFPQ_OK) return st;
             HIP_TRY(launch_gather(a, true, grid, s));
@@ -603,6 +629,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 // launch is known to have run (its count was read as nonzero,
                 // or it is the seed), so the next one runs unconditionally
                 if (first_slot == 0 && prev != 0) prev = kNoSlot;
+                a.extra = nullptr; a.extra_act = nullptr;
                 for (uint32_t j = 0; j < k; ++j, ++li) {
                     a.sel = d_NT; a.sel_act = nullptr;
                     a.src = Dbuf[(li - 1) & 1]; a.src_pitch = G; a.src_off = 0;

@@ -63,7 +63,13 @@ struct GatherArgs {
     uint32_t slot_prev;           // kNoSlot: run unconditionally
     uint32_t slot_cur;            // counts of this launch
     uint32_t seed_terms;          // seed launch: terminal transitions take part
+    const uint64_t *extra;        // seed: rows of the sparse nonterminal product [nQ][n][G] (or null:
+    const uint64_t *extra_act;    //   nonterminal transitions OR whole rows), row bitset [nQ][Pn]
 };
+
+constexpr uint32_t kEll = 16;                  // listed bits per source row in the sparse product
+constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole
+constexpr uint32_t kSparseMaxWords = 4096;     // LDS row accumulator limit (words per wavefront)
 
 struct WritebackArgs {
     uint32_t n, P, Pn, nB;
@@ -89,6 +95,11 @@ hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, 
 hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
                       uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s);
+hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
+                            const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
+                            hipStream_t s);
+hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const uint32_t *ell_idx, uint64_t *extra,
+                            uint64_t *extra_act, uint32_t grid, hipStream_t s);
 hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
                            unsigned long long *out, hipStream_t s);

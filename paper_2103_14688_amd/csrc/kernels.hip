@@ -197,6 +197,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     }
                 }
             } else {
+                if (SEED && a.extra) continue;  // done by the sparse product, OR-ed in below
                 const uint32_t N = tr.sym - a.n_terms;
                 if (SEED && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
                 const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
@@ -220,6 +221,10 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                 }
             }
         }
+        if (a.extra && test_bit(a.extra_act + (uint64_t)f * a.Pn, v)) {
+            fed = true;
+            or_row(acc, a.extra + ((uint64_t)f * a.n + v) * a.G + pass0, pass0, a.gw, lane);
+        }
         if (!fed) return false;  // no source row feeds (f, v): same in every pass
         uint64_t *trow = a.T + ((uint64_t)f * a.n + v) * a.P + a.w0 + pass0;
         uint64_t *drow = a.dn + ((uint64_t)f * a.n + v) * a.G + pass0;
@@ -241,6 +246,144 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
         row_new |= (__ballot(any) != 0);
     }
     return row_new;
+}
+
+// ---------------------------------------------------------------------------
+// sparse nonterminal product for the Kronecker seed: when the closure rows of
+// the source state hold few bits (e.g. the rows after one inverse edge),
+// OR-ing whole rows per selector bit wastes a row of loads per bit.  The rows
+// are listed instead (ELL: up to kEll set-bit positions per row, denser rows
+// flagged), and each target row gathers the listed bits of its selected
+// predecessors into an LDS row accumulator.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x) {
+    const int lane = __lane_id();
+    uint32_t incl = x;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += y;
+    }
+    return incl - x;
+}
+
+// one wavefront per (source state, row x): list the set bits of the tile
+__global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw,
+                                                      uint32_t n, const uint32_t *states, uint32_t n_states,
+                                                      uint32_t *ell_cnt, uint32_t *ell_idx) {
+    const int lane = __lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t r = wave; r < (uint64_t)n_states * n; r += nwaves) {
+        const uint32_t s = states[r / n], x = (uint32_t)(r % n);
+        const uint64_t *row = rows + ((uint64_t)s * n + x) * pitch + off;
+        uint32_t mine = 0;
+        for (uint32_t w = lane; w < gw; w += kWave) mine += (uint32_t)__popcll(row[w]);
+        uint32_t total = mine;
+        for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, kWave);
+        const uint64_t cell = (uint64_t)s * n + x;
+        if (total > kEll) {
+            if (lane == 0) ell_cnt[cell] = kEllDense;
+            continue;
+        }
+        uint32_t at = wave_excl_scan(mine);
+        for (uint32_t w = lane; w < gw && mine; w += kWave) {
+            uint64_t b = row[w];
+            while (b) {
+                const int i = __ffsll((unsigned long long)b) - 1;
+                b &= b - 1;
+                ell_idx[cell * kEll + at++] = w * 64 + (uint32_t)i;
+                --mine;
+            }
+        }
+        if (lane == 0) ell_cnt[cell] = total;
+    }
+}
+
+// one wavefront per target row (f, v): OR over every nonterminal transition
+// (s, N, f) and every new edge (x, v) of N (dNT row v) of the source row
+// (s, x), gathered bit by bit from the ELL list (or whole, if dense) into an
+// LDS accumulator of gw words; the result goes to extra[(f, v)]
+__global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32_t *ell_cnt,
+                                                       const uint32_t *ell_idx, uint64_t *extra,
+                                                       uint64_t *extra_act) {
+    extern __shared__ unsigned long long lds_acc[];
+    const int lane = __lane_id();
+    const uint32_t wib = threadIdx.x >> 6;
+    unsigned long long *acc = lds_acc + (uint64_t)wib * a.gw;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t r = wave; r < (uint64_t)a.nQ * a.n; r += nwaves) {
+        const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
+        bool cleared = false, any = false;
+        for (uint32_t t = a.in_off[f]; t < a.in_off[f + 1]; ++t) {
+            const InTrans tr = a.in_tr[t];
+            if (tr.sym < a.n_terms) continue;
+            const uint32_t N = tr.sym - a.n_terms;
+            if (!test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
+            const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
+            const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
+            for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
+                const uint32_t k = k0 + lane;
+                uint64_t wb = 0;
+                if (k < a.Pn) wb = sel[k] & sact[k];
+                uint64_t m = __ballot(wb != 0);
+                if (m && !cleared) {
+                    for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] = 0;
+                    cleared = true;
+                    __builtin_amdgcn_wave_barrier();
+                }
+                while (m) {
+                    const int j = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    uint64_t bits = readlane64(wb, j);
+                    while (bits) {
+                        const int bb = __ffsll((unsigned long long)bits) - 1;
+                        bits &= bits - 1;
+                        const uint32_t x = (k0 + (uint32_t)j) * 64u + (uint32_t)bb;
+                        const uint64_t cell = (uint64_t)tr.src * a.n + x;
+                        const uint32_t cnt = ell_cnt[cell];
+                        if (cnt == kEllDense) {
+                            const uint64_t *row = a.src + cell * a.src_pitch + a.src_off;
+                            for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] |= row[w];
+                        } else if ((uint32_t)lane < cnt) {
+                            const uint32_t u = ell_idx[cell * kEll + lane];
+                            atomicOr(&acc[u >> 6], 1ull << (u & 63));
+                        }
+                        any = true;
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+        }
+        if (!any) continue;
+        __builtin_amdgcn_wave_barrier();
+        uint64_t *out = extra + ((uint64_t)f * a.n + v) * a.G;
+        bool nz = false;
+        for (uint32_t w = lane; w < a.gw; w += kWave) {
+            const uint64_t x = acc[w];
+            out[w] = x;
+            nz |= x != 0;
+        }
+        if (__ballot(nz) && lane == 0)
+            atomicOr((unsigned long long *)&extra_act[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
+                            const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
+                            hipStream_t s) {
+    if (!n_states) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_build, dim3(grid_for((uint64_t)n_states * n * kWave)), dim3(kBlock), 0, s, rows, pitch,
+                       off, gw, n, states, n_states, ell_cnt, ell_idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const uint32_t *ell_idx, uint64_t *extra,
+                            uint64_t *extra_act, uint32_t grid, hipStream_t s) {
+    const size_t lds = (size_t)(kBlock / kWave) * a.gw * 8;
+    hipLaunchKernelGGL(k_nt_sparse, dim3(grid), dim3(kBlock), lds, s, a, ell_cnt, ell_idx, extra, extra_act);
+    return hipGetLastError();
 }
 
 template <bool SEED>
@@ -497,6 +640,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     a.T = Q.T; a.tnz = Q.tnz;
     a.act_clear = nullptr; a.clear_words = 0; a.ctr = nullptr;
     a.slot_prev = kNoSlot; a.slot_cur = 0;
+    a.extra = nullptr; a.extra_act = nullptr;
 
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;

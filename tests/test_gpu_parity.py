@@ -330,3 +330,36 @@ def test_condensed_and_levels_agree_with_witnesses():
         assert path[0][0] == u and path[-1][2] == v
         assert all((int(x), int(l), int(y)) in edges for x, l, y in path)
         assert pat.fullmatch("".join(g.labels[int(l)] for _, l, _ in path))
+
+
+# ---------------------------------------------------------------------------
+# sparse nonterminal product (ELL + LDS accumulator) against whole-row OR
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["samegen", "alias", "brackets", "random0", "random1", "random2"])
+def test_sparse_and_dense_nonterminal_product_agree(case):
+    rng = np.random.default_rng(hash(case) % 1000)
+    if case == "samegen":
+        g, _ = synth.hierarchy(3000, seed=31)
+        text = synth.SAME_GEN_G1
+    elif case == "alias":
+        g = synth.clustered(2500, cluster=(16, 64), seed=32)
+        text = synth.MEM_ALIAS
+    elif case == "brackets":
+        g = synth.erdos_renyi(700, seed=33)
+        text = synth.BRACKETS
+    else:
+        labels = [f"l{i}" for i in range(6)]
+        g = synth.powerlaw(1200, labels=tuple(labels), mean_deg=2.5, seed=34 + int(case[-1]))
+        text = synth.random_cfg(rng, [str(x) for x in rng.choice(labels, size=4, replace=False)])
+    R = rsm_mod.from_grammar(text, g.labels)
+    start = R.box_names[0]
+    want = H.oracle_grammar(g, text)[start][1]
+    outs = []
+    for dense in (False, True):
+        for tile in (0, 5):
+            graph = cfpq.Graph.from_synth(g)
+            q = cfpq.Query(R)
+            res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, dense_nt=dense)
+            check_box(res, want, g.n)
+            outs.append(res.stats()[:2])
+    assert all(o == outs[0] for o in outs)
