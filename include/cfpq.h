@@ -234,8 +234,9 @@ cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_
  * rows read and R_out the target rows fed by them (read T, write T and the
  * next frontier); for a write-back 8 * ceil(n/64) * (|F_N| + 3) per row of
  * each box; for a condensed level (CFPQ_KERNEL_COND_LEVEL, one topological
- * level of the component graph) 8 * ceil(n/64) * 2 per component completed
- * (its row written once and read once); CFPQ_KERNEL_COND_SCC sums the
+ * level of the component graph) 8 bytes per word of component rows it writes
+ * (answer rows in full, other rows only in their non-empty 512-word chunks)
+ * plus 8 bytes per word of predecessor rows it ORs in; CFPQ_KERNEL_COND_SCC sums the
  * component search (no byte count).  CFPQ_ERR_INVALID if the query was not
  * profiled. */
 enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2, CFPQ_KERNEL_COND_LEVEL = 3,

@@ -885,9 +885,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     uint32_t L = 0, hint = 32;
     uint64_t comps = 0;
     // answer pairs counted by the closure: kWave stripes per box
-    if ((uint64_t)nB * (kWave + kSlotWords) > kCtr) return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
+    if ((uint64_t)nB * (kWave + kSlotWords) > kBytesSlot)
+        return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
     unsigned long long *box_pairs = cc;   // the misc counters are not used from here on
     HIP_TRY(launch_fill((uint64_t *)box_pairs, (uint64_t)nB * kWave, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)box_pairs + kBytesSlot, 2 * kWave, 0, s));
+    unsigned long long *bytes_ctr = prof ? box_pairs + kBytesSlot : nullptr;
     std::vector<hipEvent_t> lev_ev;   // profiling: an event before each level launch, one after the chunk
     struct PoolGuard {
         std::vector<hipEvent_t> *v;
@@ -908,7 +911,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             if (prof) HIP_TRY(hipEventRecord(lev_ev[j], s));
             HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, stripe, pending, lev, d_u64(T), d_u64(res.NT), nzf,
                                       tb.is_start, l, lc + l % kCtr, lc + (l + 1) % kCtr, lc + (l + 2) % kCtr,
-                                      box_pairs, s));
+                                      box_pairs, bytes_ctr, s));
         }
         if (prof) HIP_TRY(hipEventRecord(lev_ev[k], s));
         HIP_TRY(hipMemcpyAsync(pc.h, lc, (size_t)kCtr * 8, hipMemcpyDeviceToHost, s));
@@ -958,10 +961,16 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         for (uint32_t j = 0; j < kWave; ++j) delta += pc.h[(size_t)b * kWave + j];
         delta += pc.h[(size_t)nB * kWave + (size_t)b * kSlotWords];
     }
+    uint64_t level_bytes = 0;
+    if (prof) {
+        HIP_TRY(hipMemcpy(pc.h, cc + kBytesSlot, 2 * kWave * 8, hipMemcpyDeviceToHost));
+        for (uint32_t j = 0; j < 2 * kWave; ++j) level_bytes += 8ull * pc.h[j];
+    }
     // a second iteration would seed from box-labelled transitions only: none
     res.deltas.assign({delta, 0});
     res.iterations = 2;
     if (max_iters_hit(o, 2)) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+    (void)comps;
     float ms = 0.f, ms_scc = 0.f, ms_lv = 0.f, ms_wb = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
     HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
@@ -972,7 +981,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         res.prof[CFPQ_KERNEL_COND_SCC].launches += 1;
         res.prof[CFPQ_KERNEL_COND_SCC].ms += ms_scc;
         (void)ms_lv;
-        res.prof[CFPQ_KERNEL_COND_LEVEL].bytes += 8ull * Pn * 2 * comps;
+        res.prof[CFPQ_KERNEL_COND_LEVEL].bytes += level_bytes;
         res.prof[CFPQ_KERNEL_WRITEBACK].launches += 1;
         res.prof[CFPQ_KERNEL_WRITEBACK].ms += ms_wb;
         for (uint32_t b = 0; b < nB; ++b)

@@ -25,6 +25,7 @@ namespace cfpq {
 namespace {
 
 constexpr int kCondChunks = 8;
+constexpr uint32_t kCondNodes = 64;   // consecutive nodes per work item (ballot-selected)
 static_assert(kCondChunks * kWave == kCondChunkWords, "chunk flags cover kCondChunks wavefront-widths");
 
 __device__ __forceinline__ unsigned long long wsum(unsigned long long x) {
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
                                                        const uint32_t *flags, uint32_t L,
                                                        const unsigned long long *ctr_prev,
                                                        unsigned long long *ctr_next, unsigned long long *ctr_clear,
-                                                       unsigned long long *box_pairs) {
+                                                       unsigned long long *box_pairs, unsigned long long *bytes_ctr) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_clear = 0;  // the counter level L + 2 will write
     if (*ctr_prev == 0) return;  // nothing reached level L
     const uint32_t N = g.nQ * g.n;
@@ -367,16 +368,17 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     const uint32_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
-    const uint64_t items = (((uint64_t)N + kWave - 1) / kWave) * nch;
-    unsigned long long released = 0, pairs0 = 0;
+    const uint64_t items = (((uint64_t)N + kCondNodes - 1) / kCondNodes) * nch;
+    unsigned long long released = 0, pairs0 = 0, words_w = 0, words_r = 0;
     for (uint64_t it = wave; it < items; it += nwaves) {
-        const uint64_t base = (it / nch) * kWave;
+        const uint64_t base = (it / nch) * kCondNodes;
         const uint32_t ch = (uint32_t)(it % nch);
         const uint32_t pass0 = ch * (kCondChunks * kWave);
+        const uint32_t cw = (Pn - pass0 < kCondChunks * kWave) ? Pn - pass0 : kCondChunks * kWave;  // words in chunk
         const uint32_t mine = (uint32_t)(base + lane);
         uint32_t cm = 0;
         bool at = false;
-        if (mine < N) {
+        if ((uint32_t)lane < kCondNodes && mine < N) {
             cm = scc[mine];
             at = lev[cm] == L;
         }
@@ -416,6 +418,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
                         const uint32_t ci = (uint32_t)__builtin_amdgcn_readlane((int)cx, i);
                         if (ci == last) continue;  // same row as the one just OR-ed
                         last = ci;
+                        words_r += cw;
                         const uint64_t *src = comp_row(ci, g.n, P, flags, multi, R, NT) + pass0;
 #pragma unroll
                         for (int k = 0; k < kCondChunks; ++k) {
@@ -448,6 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
                     }
                 }
                 if (lane == 0 && any_bits) nz[(uint64_t)c * nch + ch] = 1;
+                words_w += cw;
             }
             if (alias && (fq >> kFlagBoxShift) != 0) {
                 // answer pairs of a box other than 0: count directly
@@ -482,6 +486,12 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
     // box 0's answer pairs: one striped atomic per wavefront
     pairs0 = wsum(pairs0);
     if (lane == 0 && pairs0) atomicAdd(&box_pairs[wave % kWave], pairs0);
+    // words written and predecessor words requested (profiling only), striped
+    // over kWave counter pairs
+    if (bytes_ctr && lane == 0 && (words_w | words_r)) {
+        atomicAdd(&bytes_ctr[2 * (wave % kWave)], words_w);
+        atomicAdd(&bytes_ctr[2 * (wave % kWave) + 1], words_r);
+    }
 }
 
 // copy each component's row to its other members (closure blocks on request)
@@ -614,11 +624,13 @@ hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const 
                              uint32_t *indeg, uint32_t *pending, uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
                              const uint32_t *flags, uint32_t L, const unsigned long long *ctr_prev,
                              unsigned long long *ctr_next, unsigned long long *ctr_clear, unsigned long long *box_pairs,
-                             hipStream_t s) {
+                             unsigned long long *bytes_ctr, hipStream_t s) {
     const uint64_t N = (uint64_t)g.nQ * g.n;
     const uint64_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
-    hipLaunchKernelGGL(k_cond_level, dim3(wave_grid((N + kWave - 1) / kWave * nch)), dim3(kBlock), 0, s, g, P, Pn, scc,
-                       multi, indeg, pending, lev, R, NT, nz, flags, L, ctr_prev, ctr_next, ctr_clear, box_pairs);
+    hipLaunchKernelGGL(k_cond_level, dim3(wave_grid((N + kCondNodes - 1) / kCondNodes * nch)), dim3(kBlock), 0, s, g, P,
+                       Pn, scc,
+                       multi, indeg, pending, lev, R, NT, nz, flags, L, ctr_prev, ctr_next, ctr_clear, box_pairs,
+                       bytes_ctr);
     return hipGetLastError();
 }
 

@@ -135,6 +135,9 @@ constexpr uint32_t kStripes = 16;           // in-degree counters per component
 // final state of its box (its single-member rows alias the answer), box id
 // from bit 2 up
 constexpr uint32_t kStartState = 1, kAliasFinal = 2, kFlagBoxShift = 2;
+// counters of the condensed levels: kWave stripes of answer pairs per box,
+// then (at kBytesSlot) kWave (words written, predecessor words requested) pairs
+constexpr uint32_t kBytesSlot = 4096;
 hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw, uint32_t pivot,
                               uint32_t *scc, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_init(uint32_t N, const uint8_t *alive, uint32_t *color, uint8_t *found, hipStream_t s);
@@ -157,7 +160,7 @@ hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const 
                              uint32_t *indeg, uint32_t *pending, uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
                              const uint32_t *flags, uint32_t L, const unsigned long long *ctr_prev,
                              unsigned long long *ctr_next, unsigned long long *ctr_clear, unsigned long long *box_pairs,
-                             hipStream_t s);
+                             unsigned long long *bytes_ctr, hipStream_t s);
 hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint8_t *nz, uint64_t *T,
                               hipStream_t s);
 constexpr uint32_t kCondChunkWords = 512;   // chunk of a component row with its own non-empty flag
