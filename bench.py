@@ -21,6 +21,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+INT8_PEAK_TOPS = 5000.0    # dense int8 matrix-core peak, TOP/s
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the level kernel from rocprofv3 --pmc FETCH_SIZE and
@@ -41,6 +42,9 @@ def main():
     ap.add_argument("--tile-words", type=int, default=0)
     ap.add_argument("--strategy", choices=["auto", "levels", "condensed"], default="auto",
                     help="closure strategy of the plain single-query path (auto = condensed for a regular query)")
+    ap.add_argument("--nt-mode", choices=["auto", "rows", "mfma"], default="auto",
+                    help="box-labelled transitions in closure levels (grammar workloads): automatic, "
+                         "whole-row OR, or the int8 matrix-core product")
     ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400)
@@ -231,14 +235,16 @@ def other_workload(args):
     R = rsm.from_grammar(text, g.labels)
     graph = cfpq.Graph.from_synth(g)
     q = cfpq.Query(R)
+    nt_mode = {"auto": cfpq.NT_AUTO, "rows": cfpq.NT_ROWS, "mfma": cfpq.NT_MFMA}[args.nt_mode]
     rs, dt = timed(lambda: cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=args.tile_words,
-                                      profile=True), args.steps, args.warmup)
+                                      profile=True, nt_mode=nt_mode), args.steps, args.warmup)
     r = rs[-1]
     it, deltas, ms = r.stats()
     pairs = r.count(0)
     lv = r.profile(cfpq.KERNEL_LEVEL)
     sd = r.profile(cfpq.KERNEL_SEED)
     wb = r.profile(cfpq.KERNEL_WRITEBACK)
+    mf = r.profile(cfpq.KERNEL_NT_MFMA)
     achieved = lv[2] / (lv[1] * 1e-3) / 1e9 if lv[1] else 0.0
     out.update({
         "metric": f"reachable pairs/s ({args.workload})", "value": pairs / dt, "unit": "pairs/s",
@@ -249,7 +255,10 @@ def other_workload(args):
                    "all_box_pairs": {b: r.count(b) for b in R.box_names}, "iterations": it,
                    "fixpoint_ms": ms, "deltas_head": deltas[:12],
                    "level": {"launches": lv[0], "ms": lv[1], "GB": lv[2] / 1e9},
-                   "seed": {"launches": sd[0], "ms": sd[1]}, "writeback": {"launches": wb[0], "ms": wb[1]}},
+                   "seed": {"launches": sd[0], "ms": sd[1]}, "writeback": {"launches": wb[0], "ms": wb[1]},
+                   "nt_mode": args.nt_mode,
+                   "nt_mfma": {"launches": mf[0], "ms": mf[1], "int8_TOPS": mf[2] / (mf[1] * 1e9) if mf[1] else 0.0,
+                               "frac_of_int8_peak": mf[2] / (mf[1] * 1e9) / INT8_PEAK_TOPS if mf[1] else 0.0}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_gather<false> (closure frontier level)"},

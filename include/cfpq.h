@@ -143,9 +143,16 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                it; required by cfpq_extract_path (n <= 16384).
  *   keep_blocks: keep the closure blocks, required by cfpq_result_block.
  *   tile_words : source-tile width in 64-bit words (0 = automatic).
- *   dense_nt   : nonzero: never use the sparse (ELL + LDS accumulator)
- *                nonterminal product in the Kronecker seed; every selector
- *                bit ORs its whole source row (for comparison and tests).
+ *   nt_mode    : how box-labelled transitions are multiplied (levels
+ *                strategy): CFPQ_NT_AUTO = sparse rows (ELL lists + LDS
+ *                accumulators) in the Kronecker seed and whole-row OR per
+ *                selector bit in closure levels; CFPQ_NT_ROWS = whole-row OR
+ *                everywhere; CFPQ_NT_MFMA = AUTO's seed plus the exact int8
+ *                matrix-core product (v_mfma_i32_32x32x32_i8 on {0,1}
+ *                operands, thresholded) in every closure level.  AUTO never
+ *                picks the matrix cores: with sparse frontiers the dense
+ *                product moves and multiplies far more than the bit-serial OR.
+ *                The answer does not depend on the mode.
  *   profile    : record HIP events around every launch of the levels
  *                strategy (see cfpq_result_profile); adds ~1 us per launch.
  *   stream     : hipStream_t for all work of the call (NULL = null stream).
@@ -154,6 +161,7 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *   has labels; CFPQ_ERR_OOM; CFPQ_ERR_DEVICE; CFPQ_ERR_LIMIT.
  * ---------------------------------------------------------------------- */
 enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2, CFPQ_STRATEGY_CONDENSED = 3 };
+enum { CFPQ_NT_AUTO = 0, CFPQ_NT_ROWS = 1, CFPQ_NT_MFMA = 2 };
 
 typedef struct {
     uint32_t strategy;
@@ -162,7 +170,7 @@ typedef struct {
     uint32_t keep_blocks;
     uint32_t tile_words;
     uint32_t profile;
-    uint32_t dense_nt;
+    uint32_t nt_mode;
     uint32_t reserved;
     void *stream;
     const cfpq_allocator *alloc;
@@ -237,10 +245,12 @@ cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_
  * level of the component graph) 8 bytes per word of component rows it writes
  * (answer rows in full, other rows only in their non-empty 512-word chunks)
  * plus 8 bytes per word of predecessor rows it ORs in; CFPQ_KERNEL_COND_SCC sums the
- * component search (no byte count).  CFPQ_ERR_INVALID if the query was not
- * profiled. */
+ * component search (no byte count); CFPQ_KERNEL_NT_MFMA (matrix-core
+ * nonterminal products in closure levels) reports int8 operations, 2 per
+ * multiply-accumulate (65536 per v_mfma_i32_32x32x32_i8), in *bytes.
+ * CFPQ_ERR_INVALID if the query was not profiled. */
 enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2, CFPQ_KERNEL_COND_LEVEL = 3,
-       CFPQ_KERNEL_COND_SCC = 4 };
+       CFPQ_KERNEL_COND_SCC = 4, CFPQ_KERNEL_NT_MFMA = 5 };
 cfpq_status cfpq_result_profile(cfpq_result res, uint32_t kind, uint64_t *launches, double *ms,
                                 uint64_t *bytes);
 

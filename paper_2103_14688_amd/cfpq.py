@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcfpq.so")
 OK, ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_NOT_FOUND, ERR_BUFFER, ERR_LIMIT, ERR_REJECTED = 0, -1, -2, -3, -4, -5, -6, -7
 ADD_INVERSES = 1
 STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED, STRATEGY_CONDENSED = 0, 1, 2, 3
+NT_AUTO, NT_ROWS, NT_MFMA = 0, 1, 2
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUFFER", -6: "LIMIT",
            -7: "REJECTED"}
@@ -48,7 +49,7 @@ class Allocator(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("keep_rank", ctypes.c_uint32),
                 ("keep_blocks", ctypes.c_uint32), ("tile_words", ctypes.c_uint32), ("profile", ctypes.c_uint32),
-                ("dense_nt", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("nt_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("alloc", ctypes.POINTER(Allocator))]
 
 
@@ -181,8 +182,8 @@ def cfpq_rsm_destroy(r):
 
 
 def make_opts(strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-              stream=None, alloc=None, profile=False, dense_nt=False):
-    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(dense_nt), 0,
+              stream=None, alloc=None, profile=False, nt_mode=NT_AUTO):
+    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(nt_mode), 0,
                   stream, None)
     if alloc is not None:
         o.alloc = ctypes.pointer(alloc)
@@ -253,7 +254,7 @@ def cfpq_result_stats(res, cap=4096):
     return it.value, d[: min(it.value, cap)].tolist(), ms.value
 
 
-KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK, KERNEL_COND_LEVEL, KERNEL_COND_SCC = 0, 1, 2, 3, 4
+KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK, KERNEL_COND_LEVEL, KERNEL_COND_SCC, KERNEL_NT_MFMA = 0, 1, 2, 3, 4, 5
 
 
 def cfpq_result_profile(res, kind):
@@ -383,10 +384,10 @@ class Result:
 
 
 def query(graph, q, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-          stream=None, profile=False, dense_nt=False):
+          stream=None, profile=False, nt_mode=NT_AUTO):
     if stream is None:
         stream = current_stream()
-    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, dense_nt)
+    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, nt_mode)
     return Result(cfpq_query(graph.h, q.h, o), graph, q)
 
 

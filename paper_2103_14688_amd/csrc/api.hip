@@ -134,7 +134,7 @@ struct cfpq_result_s {
     struct Prof {
         uint64_t launches = 0, bytes = 0;
         double ms = 0.0;
-    } prof[5];
+    } prof[6];
     bool profiled = false;
 };
 
@@ -482,7 +482,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr, ell;
     // sparse nonterminal product in the seed: ELL lists of the source rows and
     // an LDS row accumulator per wavefront (tiles up to kSparseMaxWords words)
-    const bool sparse_nt = !p.nt_src.empty() && G <= kSparseMaxWords && !o.dense_nt;
+    const bool sparse_nt = !p.nt_src.empty() && G <= kSparseMaxWords && o.nt_mode != CFPQ_NT_ROWS;
     if (sparse_nt && !ell.alloc(al, (uint64_t)nQ * n * (kEll + 1) * 4, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (sparse product index)");
     if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
@@ -531,6 +531,28 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         if (hipEventElapsedTime(&ms, ev[2 + j], ev[3 + j]) != hipSuccess) return 0.0;
         return ms;
     };
+    // two marks per level launch: before its matrix-core products and before
+    // its gather (both recorded always); the gather ends at the next mark
+    auto prof_mark2 = [&](uint32_t j, int which) -> cfpq_status {
+        if (!prof) return CFPQ_OK;
+        hipEvent_t e = event(2 + 2 * j + (uint32_t)which);
+        if (!e) return fail(CFPQ_ERR_DEVICE, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(e, s));
+        return CFPQ_OK;
+    };
+    auto prof_span = [&](size_t i0, size_t i1) -> double {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[i0], ev[i1]) != hipSuccess) return 0.0;
+        return ms;
+    };
+    DevBuf mops;   // matrix-core instructions issued (profiling)
+    unsigned long long *mfma_ops = nullptr;
+    if (prof && p.has_calls) {
+        if (!mops.alloc(al, 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (profile counter)");
+        mfma_ops = mops.as<unsigned long long>();
+        HIP_TRY(launch_fill((uint64_t *)mfma_ops, 1, 0, s));
+    }
+    DevBuf Dx, xact;   // matrix-core product rows and their activity, allocated on first use
 
     HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_fill(d_T, qw, 0, s));
@@ -630,17 +652,49 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 // or it is the seed), so the next one runs unconditionally
                 if (first_slot == 0 && prev != 0) prev = kNoSlot;
                 a.extra = nullptr; a.extra_act = nullptr;
+                // matrix-core products for the nonterminal transitions (only on
+                // request: with sparse frontiers the dense product re-reads the
+                // selector per source word and the frontier per row tile, and
+                // loses to the bit-serial OR of selected rows by 30-70x)
+                const bool mfma = p.has_calls && o.nt_mode == CFPQ_NT_MFMA;
+                if (mfma && !Dx.p) {
+                    if (!Dx.alloc(al, fw * 8, s) || !xact.alloc(al, aw * 8, s))
+                        return fail(CFPQ_ERR_OOM, "device allocation failed (matrix-core product)");
+                }
                 for (uint32_t j = 0; j < k; ++j, ++li) {
                     a.sel = d_NT; a.sel_act = nullptr;
                     a.src = Dbuf[(li - 1) & 1]; a.src_pitch = G; a.src_off = 0;
                     a.src_act = act[(li - 1) % 3];
                     a.dn = Dbuf[li & 1]; a.actn = act[li % 3]; a.act_clear = act[(li + 1) % 3];
                     a.slot_prev = prev; a.slot_cur = slot; a.seed_terms = 0;
-                    if ((st = prof_mark(j)) != CFPQ_OK) return st;
+                    if ((st = prof_mark2(j, 0)) != CFPQ_OK) return st;
+                    if (mfma) {
+                        HIP_TRY(launch_fill(xact.as<uint64_t>(), aw, 0, s));
+                        std::vector<uint8_t> first(nQ, 1);
+                        for (uint32_t f = 0; f < nQ; ++f)
+                            for (uint32_t t = p.in_off[f]; t < p.in_off[f + 1]; ++t) {
+                                const InTrans tr = p.in_tr[t];
+                                if (tr.sym < p.n_terms) continue;
+                                MfmaArgs m{};
+                                m.n = n; m.P = P; m.Pn = Pn; m.gw = gw; m.G = G;
+                                m.sel = d_NT + (uint64_t)(tr.sym - p.n_terms) * n * P;
+                                m.src = a.src + (uint64_t)tr.src * n * G; m.src_pitch = G;
+                                m.sact = a.src_act + (uint64_t)tr.src * Pn;
+                                m.out = Dx.as<uint64_t>() + (uint64_t)f * n * G;
+                                m.out_act = xact.as<uint64_t>() + (uint64_t)f * Pn;
+                                m.first = first[f];
+                                first[f] = 0;
+                                m.ctr_prev = prev == kNoSlot ? nullptr : d_ctr + (uint64_t)prev * kSlotWords;
+                                m.mfma_ctr = prof ? mfma_ops : nullptr;
+                                HIP_TRY(launch_nt_mfma(m, s));
+                            }
+                        a.extra = Dx.as<uint64_t>(); a.extra_act = xact.as<uint64_t>();
+                    }
+                    if ((st = prof_mark2(j, 1)) != CFPQ_OK) return st;
                     HIP_TRY(launch_gather(a, false, grid, s));
                     prev = slot++;
                 }
-                if ((st = prof_mark(k)) != CFPQ_OK) return st;
+                if ((st = prof_mark2(k, 0)) != CFPQ_OK) return st;
                 if ((st = fetch(first_slot, k)) != CFPQ_OK) return st;
                 uint32_t used = k;
                 for (uint32_t j = 0; j < k; ++j)
@@ -652,7 +706,11 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                     auto &pl = res.prof[CFPQ_KERNEL_LEVEL];
                     for (uint32_t j = 0; j < k; ++j) {
                         pl.launches++;
-                        pl.ms += prof_ms(j);
+                        pl.ms += prof_span(2 + 2 * j + 1, 2 + 2 * (j + 1));
+                        if (mfma) {
+                            res.prof[CFPQ_KERNEL_NT_MFMA].launches++;
+                            res.prof[CFPQ_KERNEL_NT_MFMA].ms += prof_span(2 + 2 * j, 2 + 2 * j + 1);
+                        }
                         const uint64_t fed = pc.h[(size_t)j * kSlotWords + 1];
                         const uint64_t gained = pc.h[(size_t)j * kSlotWords + 2];
                         if (j <= used) pl.bytes += 8ull * gw * (rows_in + 3 * fed);
@@ -702,6 +760,11 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
     res.ms = ms;
     res.iterations = it;
+    if (mfma_ops) {
+        unsigned long long ops = 0;
+        HIP_TRY(hipMemcpy(&ops, mfma_ops, 8, hipMemcpyDeviceToHost));
+        res.prof[CFPQ_KERNEL_NT_MFMA].bytes = ops * 65536ull;   // 2 * 32 * 32 * 32 per instruction
+    }
     if (o.keep_blocks) res.T = std::move(T);
     return CFPQ_OK;
 }
@@ -1112,6 +1175,7 @@ bool has_calls(const cfpq_rsm_s &r) {
 
 cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
     if (o.strategy > CFPQ_STRATEGY_CONDENSED) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.nt_mode > CFPQ_NT_MFMA) return fail(CFPQ_ERR_INVALID, "unknown nt_mode");
     if (o.strategy == CFPQ_STRATEGY_CONDENSED && has_calls(r))
         return fail(CFPQ_ERR_INVALID, "condensed strategy needs an RSM without box-labelled transitions");
     if (o.keep_rank && g.n > 16384) return fail(CFPQ_ERR_LIMIT, "keep_rank needs n <= 16384");
@@ -1343,7 +1407,7 @@ extern "C" cfpq_status cfpq_result_profile(cfpq_result r, uint32_t kind, uint64_
                                            uint64_t *bytes) {
     if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
     if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile)");
-    if (kind > CFPQ_KERNEL_COND_SCC) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
+    if (kind > CFPQ_KERNEL_NT_MFMA) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
     if (launches) *launches = r->prof[kind].launches;
     if (ms) *ms = r->prof[kind].ms;
     if (bytes) *bytes = r->prof[kind].bytes;

@@ -100,6 +100,21 @@ hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, 
                             hipStream_t s);
 hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const uint32_t *ell_idx, uint64_t *extra,
                             uint64_t *extra_act, uint32_t grid, hipStream_t s);
+
+// Dense nonterminal product of one transition (s, N, f) on the matrix cores.
+struct MfmaArgs {
+    uint32_t n, P, Pn, gw, G;
+    const uint64_t *sel;          // selector rows of box N: [n][P], bits over x
+    const uint64_t *src;          // source rows of state s (tile start), pitch src_pitch, bits over sources
+    uint32_t src_pitch;
+    const uint64_t *sact;         // live source rows of state s: [Pn]
+    uint64_t *out;                // target state f rows: [n][G]
+    uint64_t *out_act;            // target state f row bitset: [Pn]
+    int first;                    // first transition into f this launch group: store, else OR
+    const unsigned long long *ctr_prev;  // skip when the previous level added nothing (or null)
+    unsigned long long *mfma_ctr; // optional: MFMA instructions issued
+};
+hipError_t launch_nt_mfma(const MfmaArgs &a, hipStream_t s);
 hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s);
 hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
                            unsigned long long *out, hipStream_t s);

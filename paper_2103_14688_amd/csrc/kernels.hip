@@ -197,7 +197,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     }
                 }
             } else {
-                if (SEED && a.extra) continue;  // done by the sparse product, OR-ed in below
+                if (a.extra) continue;  // done by the sparse or matrix-core product, OR-ed in below
                 const uint32_t N = tr.sym - a.n_terms;
                 if (SEED && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
                 const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
@@ -383,6 +383,123 @@ hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const 
                             uint64_t *extra_act, uint32_t grid, hipStream_t s) {
     const size_t lds = (size_t)(kBlock / kWave) * a.gw * 8;
     hipLaunchKernelGGL(k_nt_sparse, dim3(grid), dim3(kBlock), lds, s, a, ell_cnt, ell_idx, extra, extra_act);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dense nonterminal product on the matrix cores: for one transition (s, N, f)
+//   out[v][u] = OR_x sel[v][x] AND src[x][u]
+// as an exact int8 product with int32 accumulation (v_mfma_i32_32x32x32_i8:
+// {0,1} operands, sums <= n < 2^31), thresholded back to bits.  A wavefront
+// owns 4 x 32 target rows and one 64-bit word of sources (64 columns); per
+// 64-row step of x it transposes the 64 x 64 source block with ballots (B),
+// expands the selector words of its rows (A) and issues 16 MFMAs.
+// Any fixed assignment of the 32 k values of an MFMA to (lane group,
+// element) serves, as long as A and B use the same one: the sum runs over k.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int kMfmaTiles = 4;   // 32-row tiles per wavefront
+
+// 16 bits -> 16 bytes in {0, 1}, byte e = bit e (copies of each nibble at
+// bit offsets 0, 7, 14, 21 land one bit in each byte, without carries)
+__device__ __forceinline__ v4i expand16(uint32_t b) {
+    v4i r;
+    r[0] = (int)(((b & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[1] = (int)((((b >> 4) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[2] = (int)((((b >> 8) & 0xFu) * 0x00204081u) & 0x01010101u);
+    r[3] = (int)((((b >> 12) & 0xFu) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_nt_mfma(MfmaArgs a) {
+    if (a.ctr_prev && *a.ctr_prev == 0) return;  // the frontier ran dry
+    const int lane = __lane_id();
+    const int g = lane >> 5, col = lane & 31;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint32_t rows_per = 32 * kMfmaTiles;
+    const uint64_t tasks = (uint64_t)((a.n + rows_per - 1) / rows_per) * a.gw;
+    unsigned long long mfmas = 0;
+    for (uint64_t task = wave; task < tasks; task += nwaves) {
+        const uint32_t vb = (uint32_t)(task / a.gw) * rows_per, w = (uint32_t)(task % a.gw);
+        v16i C[kMfmaTiles][2];
+#pragma unroll
+        for (int t = 0; t < kMfmaTiles; ++t)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) C[t][c] = (v16i){0};
+        for (uint32_t xw = 0; xw < a.Pn; ++xw) {
+            const uint32_t x = xw * 64 + (uint32_t)lane;
+            uint64_t b = 0;
+            if (x < a.n && test_bit(a.sact, x)) b = a.src[(uint64_t)x * a.src_pitch + w];
+            if (__ballot(b != 0) == 0) continue;    // no live source row in this block
+            uint64_t sw[kMfmaTiles];
+            bool anysel = false;
+#pragma unroll
+            for (int t = 0; t < kMfmaTiles; ++t) {
+                const uint32_t v = vb + t * 32 + col;
+                sw[t] = v < a.n ? a.sel[(uint64_t)v * a.P + xw] : 0ull;
+                anysel |= sw[t] != 0;
+            }
+            if (__ballot(anysel) == 0) continue;    // no selector bit in this block
+            // B: column j of the 64 x 64 block = ballot of bit j over the rows
+            uint64_t cm0 = 0, cm1 = 0;
+#pragma unroll 8
+            for (int j = 0; j < 64; ++j) {
+                const uint64_t m = __ballot((b >> j) & 1ull);
+                if (col == (j & 31)) {
+                    if (j < 32) cm0 = m;
+                    else cm1 = m;
+                }
+            }
+            const int sh = 16 * g;
+            const v4i B00 = expand16((uint32_t)(cm0 >> sh) & 0xFFFFu);
+            const v4i B01 = expand16((uint32_t)(cm1 >> sh) & 0xFFFFu);
+            const v4i B10 = expand16((uint32_t)(cm0 >> (32 + sh)) & 0xFFFFu);
+            const v4i B11 = expand16((uint32_t)(cm1 >> (32 + sh)) & 0xFFFFu);
+#pragma unroll
+            for (int t = 0; t < kMfmaTiles; ++t) {
+                const v4i A0 = expand16((uint32_t)(sw[t] >> sh) & 0xFFFFu);
+                const v4i A1 = expand16((uint32_t)(sw[t] >> (32 + sh)) & 0xFFFFu);
+                C[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B00, C[t][0], 0, 0, 0);
+                C[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B10, C[t][0], 0, 0, 0);
+                C[t][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A0, B01, C[t][1], 0, 0, 0);
+                C[t][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A1, B11, C[t][1], 0, 0, 0);
+            }
+            mfmas += 4 * kMfmaTiles;
+        }
+        // threshold and pack: accumulator i of lane group g holds row
+        // 8*(i/4) + 4*g + i%4 of the tile, column col (+32 for the second half)
+#pragma unroll
+        for (int t = 0; t < kMfmaTiles; ++t) {
+            uint64_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const uint64_t b0 = __ballot(C[t][0][i] > 0), b1 = __ballot(C[t][1][i] > 0);
+                const int r0 = 8 * (i / 4) + (i % 4), r1 = r0 + 4;
+                const uint64_t w0 = (b0 & 0xFFFFFFFFull) | ((b1 & 0xFFFFFFFFull) << 32);
+                const uint64_t w1 = (b0 >> 32) | ((b1 >> 32) << 32);
+                if (lane == r0) mine = w0;
+                if (lane == r1) mine = w1;
+            }
+            const uint32_t v = vb + t * 32 + (uint32_t)lane;
+            if (lane < 32 && v < a.n) {
+                uint64_t *o = a.out + (uint64_t)v * a.G + w;
+                if (a.first)
+                    *o = mine;
+                else if (mine)
+                    atomicOr((unsigned long long *)o, mine);
+                if (mine) atomicOr((unsigned long long *)&a.out_act[v >> 6], 1ull << (v & 63));
+            }
+        }
+    }
+    if (a.mfma_ctr && lane == 0 && mfmas) atomicAdd(a.mfma_ctr, mfmas);   // wave-uniform count
+}
+
+hipError_t launch_nt_mfma(const MfmaArgs &a, hipStream_t s) {
+    const uint64_t tasks = (uint64_t)((a.n + 32 * kMfmaTiles - 1) / (32 * kMfmaTiles)) * a.gw;
+    hipLaunchKernelGGL(k_nt_mfma, dim3(grid_for(tasks * kWave)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

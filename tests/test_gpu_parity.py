@@ -333,11 +333,12 @@ def test_condensed_and_levels_agree_with_witnesses():
 
 
 # ---------------------------------------------------------------------------
-# sparse nonterminal product (ELL + LDS accumulator) against whole-row OR
+# nonterminal product: sparse rows (ELL + LDS accumulator) in the seed,
+# whole-row OR, and the int8 matrix-core product in the closure levels
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("case", ["samegen", "alias", "brackets", "random0", "random1", "random2"])
-def test_sparse_and_dense_nonterminal_product_agree(case):
-    rng = np.random.default_rng(hash(case) % 1000)
+def test_nonterminal_product_modes_agree(case):
+    rng = np.random.default_rng(sum(map(ord, case)))
     if case == "samegen":
         g, _ = synth.hierarchy(3000, seed=31)
         text = synth.SAME_GEN_G1
@@ -355,11 +356,49 @@ def test_sparse_and_dense_nonterminal_product_agree(case):
     start = R.box_names[0]
     want = H.oracle_grammar(g, text)[start][1]
     outs = []
-    for dense in (False, True):
+    for mode in (cfpq.NT_AUTO, cfpq.NT_ROWS, cfpq.NT_MFMA):
         for tile in (0, 5):
             graph = cfpq.Graph.from_synth(g)
             q = cfpq.Query(R)
-            res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, dense_nt=dense)
+            res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, nt_mode=mode)
             check_box(res, want, g.n)
             outs.append(res.stats()[:2])
     assert all(o == outs[0] for o in outs)
+
+
+# int8 matrix-core product in every closure level: target rows in 128-row
+# wavefront tasks, so sizes below, at and past a task boundary with a ragged
+# tail, tiles of 1, 3 and all source words, and relations dense enough that
+# most 64 x 64 blocks are live
+@pytest.mark.parametrize("n,tile", [(1, 0), (63, 0), (128, 0), (129, 1), (300, 3), (777, 0), (1100, 5)])
+def test_mfma_product_brackets_er(n, tile):
+    g = synth.erdos_renyi(n, p=min(1.0, 3.0 / max(n, 1)), seed=40 + n)
+    want = H.oracle_grammar(g, synth.BRACKETS)["S"][1]
+    R = rsm_mod.from_grammar(synth.BRACKETS, g.labels)
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, nt_mode=cfpq.NT_MFMA)
+    check_box(res, want, g.n)
+    _, _, ref = run(g, R, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, nt_mode=cfpq.NT_ROWS)
+    assert res.stats()[:2] == ref.stats()[:2]
+
+
+@pytest.mark.parametrize("k", [64, 150])
+def test_mfma_product_nested_chain(k):
+    # a^k b^k on a path: one nesting depth per iteration, k + 1 iterations
+    g = synth.chain("a" * k + "b" * k)
+    want = H.oracle_grammar(g, synth.BRACKETS)["S"][1]
+    R = rsm_mod.from_grammar(synth.BRACKETS, g.labels)
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_MFMA)
+    check_box(res, want, g.n)
+    assert res.stats()[0] == k + 1
+
+
+def test_mfma_product_profile_counts_operations():
+    g = synth.clustered(1200, cluster=(16, 64), seed=42)
+    R = rsm_mod.from_grammar(synth.MEM_ALIAS, g.labels)
+    want = H.oracle_grammar(g, synth.MEM_ALIAS)[R.box_names[0]][1]
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_MFMA, profile=True)
+    check_box(res, want, g.n)
+    launches, ms, ops = res.profile(cfpq.KERNEL_NT_MFMA)
+    assert launches > 0 and ms > 0 and ops > 0 and ops % 65536 == 0
+    _, _, rows = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS, profile=True)
+    assert rows.profile(cfpq.KERNEL_NT_MFMA)[0] == 0
