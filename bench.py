@@ -245,6 +245,7 @@ def other_workload(args):
     sd = r.profile(cfpq.KERNEL_SEED)
     wb = r.profile(cfpq.KERNEL_WRITEBACK)
     mf = r.profile(cfpq.KERNEL_NT_MFMA)
+    sp = r.profile(cfpq.KERNEL_NT_SPARSE)
     achieved = lv[2] / (lv[1] * 1e-3) / 1e9 if lv[1] else 0.0
     out.update({
         "metric": f"reachable pairs/s ({args.workload})", "value": pairs / dt, "unit": "pairs/s",
@@ -256,7 +257,7 @@ def other_workload(args):
                    "fixpoint_ms": ms, "deltas_head": deltas[:12],
                    "level": {"launches": lv[0], "ms": lv[1], "GB": lv[2] / 1e9},
                    "seed": {"launches": sd[0], "ms": sd[1]}, "writeback": {"launches": wb[0], "ms": wb[1]},
-                   "nt_mode": args.nt_mode,
+                   "nt_mode": args.nt_mode, "nt_sparse": {"launches": sp[0], "ms": sp[1]},
                    "nt_mfma": {"launches": mf[0], "ms": mf[1], "int8_TOPS": mf[2] / (mf[1] * 1e9) if mf[1] else 0.0,
                                "frac_of_int8_peak": mf[2] / (mf[1] * 1e9) / INT8_PEAK_TOPS if mf[1] else 0.0}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

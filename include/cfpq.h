@@ -145,8 +145,9 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *   tile_words : source-tile width in 64-bit words (0 = automatic).
  *   nt_mode    : how box-labelled transitions are multiplied (levels
  *                strategy): CFPQ_NT_AUTO = sparse rows (ELL lists + LDS
- *                accumulators) in the Kronecker seed and whole-row OR per
- *                selector bit in closure levels; CFPQ_NT_ROWS = whole-row OR
+ *                accumulators) in the Kronecker seed, and in closure levels
+ *                once a row tile spans 16 words or more (below that, whole-row
+ *                OR per selector bit); CFPQ_NT_ROWS = whole-row OR
  *                everywhere; CFPQ_NT_MFMA = AUTO's seed plus the exact int8
  *                matrix-core product (v_mfma_i32_32x32x32_i8 on {0,1}
  *                operands, thresholded) in every closure level.  AUTO never
@@ -247,10 +248,12 @@ cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_
  * plus 8 bytes per word of predecessor rows it ORs in; CFPQ_KERNEL_COND_SCC sums the
  * component search (no byte count); CFPQ_KERNEL_NT_MFMA (matrix-core
  * nonterminal products in closure levels) reports int8 operations, 2 per
- * multiply-accumulate (65536 per v_mfma_i32_32x32x32_i8), in *bytes.
+ * multiply-accumulate (65536 per v_mfma_i32_32x32x32_i8), in *bytes;
+ * CFPQ_KERNEL_NT_SPARSE sums the sparse nonterminal products of closure
+ * levels (ELL build + LDS-accumulator product; no byte count).
  * CFPQ_ERR_INVALID if the query was not profiled. */
 enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2, CFPQ_KERNEL_COND_LEVEL = 3,
-       CFPQ_KERNEL_COND_SCC = 4, CFPQ_KERNEL_NT_MFMA = 5 };
+       CFPQ_KERNEL_COND_SCC = 4, CFPQ_KERNEL_NT_MFMA = 5, CFPQ_KERNEL_NT_SPARSE = 6 };
 cfpq_status cfpq_result_profile(cfpq_result res, uint32_t kind, uint64_t *launches, double *ms,
                                 uint64_t *bytes);
 

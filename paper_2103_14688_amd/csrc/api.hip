@@ -134,7 +134,7 @@ struct cfpq_result_s {
     struct Prof {
         uint64_t launches = 0, bytes = 0;
         double ms = 0.0;
-    } prof[6];
+    } prof[7];
     bool profiled = false;
 };
 
@@ -625,7 +625,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 // activity bitset, both unused until the first level
                 uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
                 HIP_TRY(launch_ell_build(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt, ell_idx,
-                                         s));
+                                         nullptr, Pn, nullptr, s));
                 HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dbuf[1], act[2], grid, s));
                 a.extra = Dbuf[1]; a.extra_act = act[2];
             }
@@ -657,7 +657,10 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 // selector per source word and the frontier per row tile, and
                 // loses to the bit-serial OR of selected rows by 30-70x)
                 const bool mfma = p.has_calls && o.nt_mode == CFPQ_NT_MFMA;
-                if (mfma && !Dx.p) {
+                // sparse product in the levels too: frontier rows are mostly a
+                // few words, so an ELL list beats ORing the whole tile row
+                const bool lsparse = sparse_nt && o.nt_mode == CFPQ_NT_AUTO && gw >= kLevelSparseMinWords;
+                if ((mfma || lsparse) && !Dx.p) {
                     if (!Dx.alloc(al, fw * 8, s) || !xact.alloc(al, aw * 8, s))
                         return fail(CFPQ_ERR_OOM, "device allocation failed (matrix-core product)");
                 }
@@ -689,6 +692,16 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                                 HIP_TRY(launch_nt_mfma(m, s));
                             }
                         a.extra = Dx.as<uint64_t>(); a.extra_act = xact.as<uint64_t>();
+                    } else if (lsparse) {
+                        HIP_TRY(launch_fill(xact.as<uint64_t>(), aw, 0, s));
+                        uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
+                        const unsigned long long *cp =
+                            prev == kNoSlot ? nullptr : d_ctr + (uint64_t)prev * kSlotWords;
+                        HIP_TRY(launch_ell_build(a.src, G, 0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt,
+                                                 ell_idx, a.src_act, Pn, cp, s));
+                        a.extra = nullptr;   // the product reads the selector, not extra
+                        HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dx.as<uint64_t>(), xact.as<uint64_t>(), grid, s));
+                        a.extra = Dx.as<uint64_t>(); a.extra_act = xact.as<uint64_t>();
                     }
                     if ((st = prof_mark2(j, 1)) != CFPQ_OK) return st;
                     HIP_TRY(launch_gather(a, false, grid, s));
@@ -707,9 +720,10 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                     for (uint32_t j = 0; j < k; ++j) {
                         pl.launches++;
                         pl.ms += prof_span(2 + 2 * j + 1, 2 + 2 * (j + 1));
-                        if (mfma) {
-                            res.prof[CFPQ_KERNEL_NT_MFMA].launches++;
-                            res.prof[CFPQ_KERNEL_NT_MFMA].ms += prof_span(2 + 2 * j, 2 + 2 * j + 1);
+                        if (mfma || lsparse) {
+                            auto &pp = res.prof[mfma ? CFPQ_KERNEL_NT_MFMA : CFPQ_KERNEL_NT_SPARSE];
+                            pp.launches++;
+                            pp.ms += prof_span(2 + 2 * j, 2 + 2 * j + 1);
                         }
                         const uint64_t fed = pc.h[(size_t)j * kSlotWords + 1];
                         const uint64_t gained = pc.h[(size_t)j * kSlotWords + 2];
@@ -1407,7 +1421,7 @@ extern "C" cfpq_status cfpq_result_profile(cfpq_result r, uint32_t kind, uint64_
                                            uint64_t *bytes) {
     if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
     if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile)");
-    if (kind > CFPQ_KERNEL_NT_MFMA) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
+    if (kind > CFPQ_KERNEL_NT_SPARSE) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
     if (launches) *launches = r->prof[kind].launches;
     if (ms) *ms = r->prof[kind].ms;
     if (bytes) *bytes = r->prof[kind].bytes;

@@ -69,6 +69,9 @@ struct GatherArgs {
 
 constexpr uint32_t kEll = 16;                  // listed bits per source row in the sparse product
 constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole
+// closure levels use the sparse product from this many words per row tile
+// (narrower rows are ORed whole at no greater cost)
+constexpr uint32_t kLevelSparseMinWords = 16;
 constexpr uint32_t kSparseMaxWords = 4096;     // LDS row accumulator limit (words per wavefront)
 
 struct WritebackArgs {
@@ -95,9 +98,11 @@ hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, 
 hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
                       uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s);
+// ELL lists of the rows of the given states (act: skip rows whose activity
+// bit is clear, may be null; ctr_prev: skip the launch when that count is 0)
 hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
                             const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
-                            hipStream_t s);
+                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s);
 hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const uint32_t *ell_idx, uint64_t *extra,
                             uint64_t *extra_act, uint32_t grid, hipStream_t s);
 

@@ -269,12 +269,17 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x) {
 // one wavefront per (source state, row x): list the set bits of the tile
 __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw,
                                                       uint32_t n, const uint32_t *states, uint32_t n_states,
-                                                      uint32_t *ell_cnt, uint32_t *ell_idx) {
+                                                      uint32_t *ell_cnt, uint32_t *ell_idx, const uint64_t *act,
+                                                      uint32_t Pn, const unsigned long long *ctr_prev) {
+    if (ctr_prev && *ctr_prev == 0) return;  // the frontier ran dry
     const int lane = __lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     for (uint64_t r = wave; r < (uint64_t)n_states * n; r += nwaves) {
         const uint32_t s = states[r / n], x = (uint32_t)(r % n);
+        // rows marked inactive are never looked up (the product tests the
+        // same activity bit first)
+        if (act && !test_bit(act + (uint64_t)s * Pn, x)) continue;
         const uint64_t *row = rows + ((uint64_t)s * n + x) * pitch + off;
         uint32_t mine = 0;
         for (uint32_t w = lane; w < gw; w += kWave) mine += (uint32_t)__popcll(row[w]);
@@ -306,6 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
 __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32_t *ell_cnt,
                                                        const uint32_t *ell_idx, uint64_t *extra,
                                                        uint64_t *extra_act) {
+    if (a.slot_prev != kNoSlot && a.ctr[(uint64_t)a.slot_prev * kSlotWords] == 0) return;  // frontier ran dry
     extern __shared__ unsigned long long lds_acc[];
     const int lane = __lane_id();
     const uint32_t wib = threadIdx.x >> 6;
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             const InTrans tr = a.in_tr[t];
             if (tr.sym < a.n_terms) continue;
             const uint32_t N = tr.sym - a.n_terms;
-            if (!test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
+            if (a.sel_act && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
             const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
             const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
             for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
@@ -335,23 +341,33 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                 while (m) {
                     const int j = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1;
-                    uint64_t bits = readlane64(wb, j);
-                    while (bits) {
-                        const int bb = __ffsll((unsigned long long)bits) - 1;
-                        bits &= bits - 1;
-                        const uint32_t x = (k0 + (uint32_t)j) * 64u + (uint32_t)bb;
-                        const uint64_t cell = (uint64_t)tr.src * a.n + x;
-                        const uint32_t cnt = ell_cnt[cell];
-                        if (cnt == kEllDense) {
-                            const uint64_t *row = a.src + cell * a.src_pitch + a.src_off;
-                            for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] |= row[w];
-                        } else if ((uint32_t)lane < cnt) {
-                            const uint32_t u = ell_idx[cell * kEll + lane];
+                    // the set bits of one selector word at once, lane i taking
+                    // source row 64 (k0 + j) + i: its ELL entries go to the
+                    // accumulator by LDS atomics; dense rows are ORed whole by
+                    // the wave afterwards, one at a time
+                    const uint64_t bits = readlane64(wb, j);
+                    const uint32_t xb = (k0 + (uint32_t)j) * 64u;
+                    const bool mine = (bits >> lane) & 1ull;
+                    const uint64_t cell = (uint64_t)tr.src * a.n + xb + (uint32_t)lane;
+                    const uint32_t cnt = mine ? ell_cnt[cell] : 0u;
+                    const bool dense = cnt == kEllDense;
+                    if (!dense) {
+                        const uint32_t *idx = ell_idx + cell * kEll;
+                        for (uint32_t e = 0; e < cnt; ++e) {
+                            const uint32_t u = idx[e];
                             atomicOr(&acc[u >> 6], 1ull << (u & 63));
                         }
-                        any = true;
-                        __builtin_amdgcn_wave_barrier();
                     }
+                    uint64_t dm = __ballot(dense);
+                    while (dm) {
+                        const int d = __ffsll((unsigned long long)dm) - 1;
+                        dm &= dm - 1;
+                        const uint64_t *row = a.src + ((uint64_t)tr.src * a.n + xb + (uint32_t)d) * a.src_pitch +
+                                              a.src_off;
+                        for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] |= row[w];
+                    }
+                    any = true;
+                    __builtin_amdgcn_wave_barrier();
                 }
             }
         }
@@ -372,10 +388,10 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
 
 hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
                             const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
-                            hipStream_t s) {
+                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s) {
     if (!n_states) return hipSuccess;
     hipLaunchKernelGGL(k_ell_build, dim3(grid_for((uint64_t)n_states * n * kWave)), dim3(kBlock), 0, s, rows, pitch,
-                       off, gw, n, states, n_states, ell_cnt, ell_idx);
+                       off, gw, n, states, n_states, ell_cnt, ell_idx, act, Pn, ctr_prev);
     return hipGetLastError();
 }
 

@@ -357,7 +357,7 @@ def test_nonterminal_product_modes_agree(case):
     want = H.oracle_grammar(g, text)[start][1]
     outs = []
     for mode in (cfpq.NT_AUTO, cfpq.NT_ROWS, cfpq.NT_MFMA):
-        for tile in (0, 5):
+        for tile in (0, 5, 20):
             graph = cfpq.Graph.from_synth(g)
             q = cfpq.Query(R)
             res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=tile, nt_mode=mode)
@@ -402,3 +402,15 @@ def test_mfma_product_profile_counts_operations():
     assert launches > 0 and ms > 0 and ops > 0 and ops % 65536 == 0
     _, _, rows = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS, profile=True)
     assert rows.profile(cfpq.KERNEL_NT_MFMA)[0] == 0
+
+
+def test_sparse_product_runs_in_closure_levels():
+    g = synth.clustered(3000, cluster=(16, 64), seed=43)
+    R = rsm_mod.from_grammar(synth.MEM_ALIAS, g.labels)
+    want = H.oracle_grammar(g, synth.MEM_ALIAS)[R.box_names[0]][1]
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_AUTO, profile=True)
+    check_box(res, want, g.n)
+    assert res.profile(cfpq.KERNEL_NT_SPARSE)[0] > 0
+    _, _, rows = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS, profile=True)
+    assert rows.profile(cfpq.KERNEL_NT_SPARSE)[0] == 0
+    assert rows.stats()[:2] == res.stats()[:2]
