@@ -72,13 +72,15 @@ typedef struct {
  * flags: CFPQ_ADD_INVERSES adds, for every label l, the inverse label
  *   n_labels + l carrying (v, u) for each (u, l, v) (the inverse relation of
  *   the same-generation and alias queries, Sec. 4.2); the graph then has
- *   2 * n_labels labels.
+ *   2 * n_labels labels.  CFPQ_DEVICE_PTRS: src/label/dst are device
+ *   pointers (read on the given stream before the call returns).
  * Errors: CFPQ_ERR_INVALID if n_vertices == 0, n_labels == 0, a vertex
  *   >= n_vertices, a label >= n_labels, a NULL array with n_edges > 0, or
  *   more than 2^32 - 1 distinct edges.
  * The graph stays resident on the current device until cfpq_graph_destroy.
  * ---------------------------------------------------------------------- */
 #define CFPQ_ADD_INVERSES 1u
+#define CFPQ_DEVICE_PTRS 2u
 
 cfpq_status cfpq_graph_create(uint32_t n_vertices, uint32_t n_labels, const uint32_t *src,
                               const uint32_t *label, const uint32_t *dst, uint64_t n_edges,
@@ -157,6 +159,18 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *   profile    : record HIP events around every launch of the levels
  *                strategy (see cfpq_result_profile); adds ~1 us per launch.
  *   stream     : hipStream_t for all work of the call (NULL = null stream).
+ *   src_mask, dst_mask: host bitsets of ceil(n/64) words (bit v of word
+ *                v / 64, LSB first; bits >= n ignored), NULL = every vertex.
+ *                The start box's relation is restricted to sources in
+ *                src_mask and targets in dst_mask (the multiple-source
+ *                variant, Sec. 6): count, hash, bitmap, pairs and witness
+ *                paths of that box see only those pairs.  For a query
+ *                without box-labelled transitions only the masked sources
+ *                are searched (work shrinks with the mask); for grammars
+ *                the nonterminals still need every source, so the mask
+ *                filters the answer.  Other boxes' relations, closure
+ *                blocks and per-iteration counts are not masked.  Not
+ *                accepted by cfpq_query_batch (graphs differ in size).
  * The call returns after the fixpoint has finished on the device.
  * Errors: CFPQ_ERR_INVALID if the RSM uses more terminals than the graph
  *   has labels; CFPQ_ERR_OOM; CFPQ_ERR_DEVICE; CFPQ_ERR_LIMIT.
@@ -175,6 +189,8 @@ typedef struct {
     uint32_t reserved;
     void *stream;
     const cfpq_allocator *alloc;
+    const uint64_t *src_mask;
+    const uint64_t *dst_mask;
 } cfpq_query_opts;
 
 cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opts *opts, cfpq_result *out);

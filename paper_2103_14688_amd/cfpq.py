@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libcfpq.so")
 
 OK, ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_NOT_FOUND, ERR_BUFFER, ERR_LIMIT, ERR_REJECTED = 0, -1, -2, -3, -4, -5, -6, -7
 ADD_INVERSES = 1
+DEVICE_PTRS = 2
 STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED, STRATEGY_CONDENSED = 0, 1, 2, 3
 NT_AUTO, NT_ROWS, NT_MFMA = 0, 1, 2
 
@@ -50,7 +51,8 @@ class QueryOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("keep_rank", ctypes.c_uint32),
                 ("keep_blocks", ctypes.c_uint32), ("tile_words", ctypes.c_uint32), ("profile", ctypes.c_uint32),
                 ("nt_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("stream", ctypes.c_void_p), ("alloc", ctypes.POINTER(Allocator))]
+                ("stream", ctypes.c_void_p), ("alloc", ctypes.POINTER(Allocator)),
+                ("src_mask", ctypes.c_void_p), ("dst_mask", ctypes.c_void_p)]
 
 
 _lib = None
@@ -145,12 +147,26 @@ def current_stream():
 # ---------------------------------------------------------------------------
 
 def cfpq_graph_create(n, n_labels, src, label, dst, flags=0, alloc=None, stream=None):
+    """Edge arrays: host arrays (anything numpy converts), or, with
+    DEVICE_PTRS in flags, int32/uint32 device tensors (torch) of equal length."""
     lib = load()
-    src, label, dst = _u32(src), _u32(label), _u32(dst)
-    if not (len(src) == len(label) == len(dst)):
-        raise ValueError("edge arrays differ in length")
+    if flags & DEVICE_PTRS:
+        import torch
+        arrs = [x.contiguous() for x in (src, label, dst)]
+        if any(x.dtype not in (torch.int32, torch.uint32) or not x.is_cuda for x in arrs):
+            raise ValueError("DEVICE_PTRS needs 32-bit integer device tensors")
+        m = arrs[0].numel()
+        if any(x.numel() != m for x in arrs):
+            raise ValueError("edge arrays differ in length")
+        ptrs = [ctypes.c_void_p(x.data_ptr()) for x in arrs]
+    else:
+        src, label, dst = _u32(src), _u32(label), _u32(dst)
+        if not (len(src) == len(label) == len(dst)):
+            raise ValueError("edge arrays differ in length")
+        m = len(src)
+        ptrs = [_ptr(src), _ptr(label), _ptr(dst)]
     out = ctypes.c_void_p()
-    _check(lib.cfpq_graph_create(n, n_labels, _ptr(src), _ptr(label), _ptr(dst), len(src), flags,
+    _check(lib.cfpq_graph_create(n, n_labels, ptrs[0], ptrs[1], ptrs[2], m, flags,
                                  ctypes.byref(alloc) if alloc is not None else None, stream, ctypes.byref(out)))
     return out.value
 
@@ -181,12 +197,37 @@ def cfpq_rsm_destroy(r):
     load().cfpq_rsm_destroy(r)
 
 
+def vertex_mask(mask, n):
+    """A vertex mask as ceil(n/64) uint64 words: from a bool array of length n
+    or from such words; None stays None."""
+    if mask is None:
+        return None
+    m = np.asarray(mask)
+    words = (n + 63) // 64
+    if m.dtype == np.bool_:
+        if m.shape != (n,):
+            raise ValueError("a boolean mask needs one entry per vertex")
+        bits = np.zeros(words * 64, dtype=np.uint8)
+        bits[:n] = m
+        return np.ascontiguousarray(np.packbits(bits, bitorder="little").view(np.uint64))
+    m = np.ascontiguousarray(m, dtype=np.uint64)
+    if m.shape != (words,):
+        raise ValueError(f"a word mask needs {words} uint64 words")
+    return m
+
+
 def make_opts(strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-              stream=None, alloc=None, profile=False, nt_mode=NT_AUTO):
+              stream=None, alloc=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None):
+    """Options struct; masks must be word arrays (vertex_mask) that the caller
+    keeps alive until the call returns."""
     o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(nt_mode), 0,
-                  stream, None)
+                  stream, None, None, None)
     if alloc is not None:
         o.alloc = ctypes.pointer(alloc)
+    if src_mask is not None:
+        o.src_mask = src_mask.ctypes.data
+    if dst_mask is not None:
+        o.dst_mask = dst_mask.ctypes.data
     return o
 
 
@@ -385,10 +426,14 @@ class Result:
 
 
 def query(graph, q, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-          stream=None, profile=False, nt_mode=NT_AUTO):
+          stream=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None):
+    """src_mask / dst_mask: bool arrays of length n or ceil(n/64) uint64
+    words restricting the start box's sources / targets (None = all)."""
     if stream is None:
         stream = current_stream()
-    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, nt_mode)
+    sm, dm = vertex_mask(src_mask, graph.n), vertex_mask(dst_mask, graph.n)
+    o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, nt_mode,
+                  sm, dm)
     return Result(cfpq_query(graph.h, q.h, o), graph, q)
 
 

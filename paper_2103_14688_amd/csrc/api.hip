@@ -124,6 +124,7 @@ struct cfpq_result_s {
     DevBuf T;         // [nQ][n][P] closure rows (keep_blocks)
     DevBuf rank;      // [nB][n][n] u8 (keep_rank)
     DevBuf scratch;   // small device scratch for accessors
+    DevBuf src_mask;  // [Pn] source mask of the start box (optional)
     uint32_t iterations = 0;
     std::vector<uint64_t> deltas;
     double ms = 0.0;
@@ -150,8 +151,26 @@ extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const ui
     *out = nullptr;
     if (n == 0 || n_labels == 0) return fail(CFPQ_ERR_INVALID, "graph needs n_vertices >= 1 and n_labels >= 1");
     if (n_edges && (!src || !label || !dst)) return fail(CFPQ_ERR_INVALID, "edge array is NULL");
-    if (flags & ~CFPQ_ADD_INVERSES) return fail(CFPQ_ERR_INVALID, "unknown flag");
+    if (flags & ~(CFPQ_ADD_INVERSES | CFPQ_DEVICE_PTRS)) return fail(CFPQ_ERR_INVALID, "unknown flag");
     if (n == 0xFFFFFFFFu) return fail(CFPQ_ERR_INVALID, "too many vertices");
+    std::vector<uint32_t> h_src, h_lbl, h_dst;   // host copies of device edge arrays
+    if ((flags & CFPQ_DEVICE_PTRS) && n_edges) {
+        try {
+            h_src.resize(n_edges);
+            h_lbl.resize(n_edges);
+            h_dst.resize(n_edges);
+        } catch (...) {
+            return fail(CFPQ_ERR_OOM, "host allocation failed");
+        }
+        hipStream_t cs = (hipStream_t)stream;
+        HIP_TRY(hipMemcpyAsync(h_src.data(), src, n_edges * 4, hipMemcpyDeviceToHost, cs));
+        HIP_TRY(hipMemcpyAsync(h_lbl.data(), label, n_edges * 4, hipMemcpyDeviceToHost, cs));
+        HIP_TRY(hipMemcpyAsync(h_dst.data(), dst, n_edges * 4, hipMemcpyDeviceToHost, cs));
+        HIP_TRY(hipStreamSynchronize(cs));
+        src = h_src.data();
+        label = h_lbl.data();
+        dst = h_dst.data();
+    }
     const bool inv = flags & CFPQ_ADD_INVERSES;
     const uint32_t L = inv ? 2 * n_labels : n_labels;
     if (inv && n_labels > 0x7FFFFFFFu) return fail(CFPQ_ERR_INVALID, "too many labels");
@@ -561,7 +580,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
     HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), (uint64_t)nB * Pn, 0, s));
     HIP_TRY(launch_fill((uint64_t *)d_ctr, ring_words, 0, s));
-    HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, s));
+    HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, res.src_mask.as<uint64_t>(), s));
     HIP_TRY(launch_eps(d_NT, d_dNT, dnt_act.as<uint64_t>(), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
                        Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
 
@@ -839,6 +858,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     pg.goff = g.off.as<uint32_t>(); pg.gidx = g.idx.as<uint32_t>();
     pg.soff = g.soff.as<uint32_t>(); pg.sidx = g.sidx.as<uint32_t>();
     pg.in_off = tb.in_off; pg.in_tr = tb.in_tr; pg.out_off = tb.out_off; pg.out_tr = tb.out_tr;
+    pg.src_mask = res.src_mask.as<uint64_t>();
 
     hipEvent_t ev[4];
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
@@ -955,7 +975,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     // ---- condensation, one topological level per launch
     HIP_TRY(launch_fill((uint64_t *)fw, (Nu * 4 * 2) / 8, 0, s));  // lev (reuses fw/bw) := 0
     HIP_TRY(launch_cond_count(pg, scc, size, stripe, s));
-    HIP_TRY(launch_cond_seed(n, P, Pn, nQ, tb.starts, nB, scc, size, d_u64(T), nzf, s));
+    HIP_TRY(launch_cond_seed(n, P, Pn, nQ, tb.starts, nB, scc, size, d_u64(T), nzf, res.src_mask.as<uint64_t>(), s));
     // level L's component count lives in lc[L % kCtr]; the launch for level L
     // clears lc[(L + 2) % kCtr] before level L + 1 writes it
     HIP_TRY(launch_cond_roots(N, scc, stripe, pending, lev, lc + 0, s));
@@ -1223,12 +1243,45 @@ extern "C" cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opt
     std::unique_ptr<cfpq_result_s> res(new_result(*g, *r, o));
     if (!res) return fail(CFPQ_ERR_OOM, "host allocation failed");
     try {
+        // masks: device copies with the bits past n cleared
+        DevBuf dmask;
+        const uint32_t Pn = (g->n + 63) / 64;
+        hipStream_t s = (hipStream_t)o.stream;
+        uint64_t *d_src = nullptr, *d_dst = nullptr;
+        if (o.src_mask || o.dst_mask) {
+            if (!dmask.alloc(&res->alloc, 2ull * Pn * 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (masks)");
+            std::vector<uint64_t> h(2ull * Pn, ~0ull);
+            if (o.src_mask) std::memcpy(h.data(), o.src_mask, (size_t)Pn * 8);
+            if (o.dst_mask) std::memcpy(h.data() + Pn, o.dst_mask, (size_t)Pn * 8);
+            if (g->n % 64) {
+                const uint64_t keep = (1ull << (g->n % 64)) - 1;
+                h[Pn - 1] &= keep;
+                h[2 * Pn - 1] &= keep;
+            }
+            HIP_TRY(hipMemcpyAsync(dmask.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            d_src = o.src_mask ? dmask.as<uint64_t>() : nullptr;
+            d_dst = o.dst_mask ? dmask.as<uint64_t>() + Pn : nullptr;
+            // a query without box-labelled transitions searches only the
+            // masked sources; with them every source is needed
+            if (d_src && !has_calls(*r)) {
+                if (!res->src_mask.alloc(&res->alloc, (size_t)Pn * 8, s))
+                    return fail(CFPQ_ERR_OOM, "device allocation failed (masks)");
+                HIP_TRY(hipMemcpyAsync(res->src_mask.p, d_src, (size_t)Pn * 8, hipMemcpyDeviceToDevice, s));
+            }
+        }
         if (use_fused(*g, *r, o)) {
             std::vector<FusedJob> jobs(1);
             if ((st = prepare_fused(*g, *r, o, *res, jobs[0])) != CFPQ_OK) return st;
             if ((st = run_fused_jobs(jobs, o, &res->alloc)) != CFPQ_OK) return st;
         } else {
             if ((st = run_big(*g, *r, o, *res)) != CFPQ_OK) return st;
+        }
+        if (d_src || d_dst) {
+            const uint64_t P = res->P;
+            HIP_TRY(launch_mask_rows(res->NT.as<uint64_t>() + (uint64_t)r->start_box * g->n * P, g->n, (uint32_t)P,
+                                     Pn, d_src, d_dst, s));
+            HIP_TRY(hipStreamSynchronize(s));
         }
     } catch (const std::bad_alloc &) {
         return fail(CFPQ_ERR_OOM, "host allocation failed");
@@ -1243,6 +1296,7 @@ extern "C" cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm
     for (uint32_t i = 0; i < k; ++i) results[i] = nullptr;
     cfpq_query_opts o{};
     if (opts) o = *opts;
+    if (o.src_mask || o.dst_mask) return fail(CFPQ_ERR_INVALID, "vertex masks are not accepted by the batched call");
     std::vector<std::unique_ptr<cfpq_result_s>> res(k);
     cfpq_status st = CFPQ_OK;
     try {
@@ -1540,6 +1594,12 @@ extern "C" cfpq_status cfpq_extract_path(cfpq_result r, uint32_t box, uint32_t u
     }
     const uint8_t rk = r->h_rank[((uint64_t)box * r->n + u) * r->n + v];
     if (rk == 0xFF) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
+    {   // the relation as returned (a vertex mask may have removed the pair)
+        uint64_t word = 0;
+        HIP_TRY(hipMemcpy(&word, r->NT.as<uint64_t>() + ((uint64_t)box * r->n + v) * r->P + (u >> 6), 8,
+                          hipMemcpyDeviceToHost));
+        if (!((word >> (u & 63)) & 1ull)) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
+    }
     std::vector<uint32_t> out;
     Witness w{r, &out, (uint64_t)1 << 26};
     if (!w.expand(box, u, v, rk)) {

@@ -28,6 +28,8 @@ constexpr int kCondChunks = 8;
 constexpr uint32_t kCondNodes = 64;   // consecutive nodes per work item (ballot-selected)
 static_assert(kCondChunks * kWave == kCondChunkWords, "chunk flags cover kCondChunks wavefront-widths");
 
+__device__ __forceinline__ bool mask_bit(const uint64_t *bits, uint32_t i) { return (bits[i >> 6] >> (i & 63)) & 1ull; }
+
 __device__ __forceinline__ unsigned long long wsum(unsigned long long x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
     return x;
@@ -305,10 +307,12 @@ __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t
 // (a single-member component's row is written whole, seed included, when its
 // topological level is processed)
 __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts,
-                            const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz, uint32_t nch) {
+                            const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz, uint32_t nch,
+                            const uint64_t *mask) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)n_starts * n;
          i += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t s = starts[i / n], u = (uint32_t)(i % n);
+        if (mask && !mask_bit(mask, u)) continue;
         const uint32_t c = scc[s * n + u];
         if (multi[c]) {
             atomicOr((unsigned long long *)&R[(uint64_t)c * P + (u >> 6)], 1ull << (u & 63));
@@ -394,7 +398,8 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
             const bool alias = single && (fq & kAliasFinal);
             uint64_t *row = comp_row(c, g.n, P, flags, multi, R, NT) + pass0;
             // seed bit of a single-member component: (start, v) is where source v begins
-            const uint64_t seed_word = (single && (fq & kStartState)) ? 1ull << (v & 63) : 0ull;
+            const uint64_t seed_word =
+                (single && (fq & kStartState) && (!g.src_mask || mask_bit(g.src_mask, v))) ? 1ull << (v & 63) : 0ull;
             const uint32_t seed_w = v >> 6;
             uint64_t acc[kCondChunks];
 #pragma unroll
@@ -605,12 +610,12 @@ hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *
 
 hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, const uint32_t *starts,
                             uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
-                            hipStream_t s) {
+                            const uint64_t *mask, hipStream_t s) {
     const uint64_t N = (uint64_t)nQ * n;
     const uint32_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
     hipLaunchKernelGGL(k_cond_zero_multi, dim3(wave_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R);
     hipLaunchKernelGGL(k_cond_seed, dim3(node_grid((uint64_t)n * n_starts)), dim3(kBlock), 0, s, n, P, starts,
-                       n_starts, scc, multi, R, nz, nch);
+                       n_starts, scc, multi, R, nz, nch, mask);
     return hipGetLastError();
 }
 

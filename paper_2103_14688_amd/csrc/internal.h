@@ -93,8 +93,15 @@ struct WritebackArgs {
 // kernels.hip
 hipError_t launch_fill(uint64_t *p, uint64_t words, uint64_t value, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t *p, uint64_t bytes, hipStream_t s);
+// trivial bits of the box-start rows: (start, v) holds source bit v, for v in
+// mask (null = every vertex)
 hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
-                            const uint32_t *states, uint32_t n_states, hipStream_t s);
+                            const uint32_t *states, uint32_t n_states, const uint64_t *mask, hipStream_t s);
+// vertex masks on one box's rows [n][P] (row v = sources): rows of targets
+// outside dst lose every bit, the others keep the sources in src (either
+// mask may be null)
+hipError_t launch_mask_rows(uint64_t *rows, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *src,
+                            const uint64_t *dst, hipStream_t s);
 hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *rank, uint32_t n,
                       uint32_t P, uint32_t Pn, const uint32_t *boxes, uint32_t nb, hipStream_t s);
 hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s);
@@ -137,6 +144,7 @@ struct ProdGraph {
     const uint32_t *in_off, *out_off;
     const InTrans *in_tr;          // per target state: (source state, label)
     const InTrans *out_tr;         // per source state: (target state in .src, label)
+    const uint64_t *src_mask;      // sources searched ([ceil(n/64)] bits), null = all
 };
 
 // condense.hip
@@ -173,7 +181,7 @@ hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *
                              hipStream_t s);
 hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, const uint32_t *starts,
                             uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
-                            hipStream_t s);
+                            const uint64_t *mask, hipStream_t s);
 hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *stripe, uint32_t *pending,
                              uint32_t *lev, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint32_t *multi,

@@ -77,30 +77,49 @@ hipError_t launch_fill_u8(uint8_t *p, uint64_t bytes, hipStream_t s) {
 // from source v starts.  T rows of states[i] get bit v in row v.
 __device__ void seed_diag_body(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
                                const uint32_t *states, uint32_t n_states, uint64_t tid,
-                               uint64_t nthreads) {
+                               uint64_t nthreads, const uint64_t *mask = nullptr) {
     for (uint64_t i = tid; i < (uint64_t)n_states * n; i += nthreads) {
         uint32_t s = states[i / n], v = (uint32_t)(i % n);
+        if (mask && !test_bit(mask, v)) continue;
         T[((uint64_t)s * n + v) * P + (v >> 6)] |= 1ull << (v & 63);
     }
     for (uint64_t i = tid; i < (uint64_t)n_states * Pn; i += nthreads) {
         uint32_t s = states[i / Pn], k = (uint32_t)(i % Pn);
         uint32_t hi = n - k * 64;
-        tnz[(uint64_t)s * Pn + k] = hi >= 64 ? ~0ull : ((1ull << hi) - 1);
+        const uint64_t m = mask ? mask[k] : ~0ull;   // mask bits past n are clear
+        tnz[(uint64_t)s * Pn + k] = (hi >= 64 ? ~0ull : ((1ull << hi) - 1)) & m;
     }
 }
 
 __global__ void k_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
-                            const uint32_t *states, uint32_t n_states) {
+                            const uint32_t *states, uint32_t n_states, const uint64_t *mask) {
     seed_diag_body(T, tnz, n, P, Pn, states, n_states,
                    (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
-                   (uint64_t)gridDim.x * blockDim.x);
+                   (uint64_t)gridDim.x * blockDim.x, mask);
 }
 
 hipError_t launch_seed_diag(uint64_t *T, uint64_t *tnz, uint32_t n, uint32_t P, uint32_t Pn,
-                            const uint32_t *states, uint32_t n_states, hipStream_t s) {
+                            const uint32_t *states, uint32_t n_states, const uint64_t *mask, hipStream_t s) {
     if (!n_states) return hipSuccess;
     hipLaunchKernelGGL(k_seed_diag, dim3(grid_for((uint64_t)n_states * n)), dim3(kBlock), 0, s, T,
-                       tnz, n, P, Pn, states, n_states);
+                       tnz, n, P, Pn, states, n_states, mask);
+    return hipGetLastError();
+}
+
+__global__ void k_mask_rows(uint64_t *rows, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *src,
+                            const uint64_t *dst) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)n * Pn;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(i / Pn), w = (uint32_t)(i % Pn);
+        uint64_t &x = rows[(uint64_t)v * P + w];
+        if (dst && !test_bit(dst, v)) x = 0;
+        else if (src) x &= src[w];
+    }
+}
+
+hipError_t launch_mask_rows(uint64_t *rows, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *src,
+                            const uint64_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_rows, dim3(grid_for((uint64_t)n * Pn)), dim3(kBlock), 0, s, rows, n, P, Pn, src, dst);
     return hipGetLastError();
 }
 

@@ -138,3 +138,24 @@ def test_synth_generators_are_seeded_and_shaped():
     assert len(graphs) == 4 and len(qs) == 50
     for gi, kind, text in qs:
         (rsm_mod.from_regex if kind == "regex" else rsm_mod.from_grammar)(text, labels)
+
+
+def test_vertex_mask_packing():
+    n = 130
+    m = np.zeros(n, dtype=bool)
+    m[[0, 63, 64, 129]] = True
+    w = cfpq.vertex_mask(m, n)
+    assert w.dtype == np.uint64 and w.shape == (3,)
+    assert [int(x) for x in w] == [1 | (1 << 63), 1, 2]
+    assert cfpq.vertex_mask(None, n) is None
+    assert np.array_equal(cfpq.vertex_mask(w, n), w)
+    with pytest.raises(ValueError):
+        cfpq.vertex_mask(np.zeros(n - 1, dtype=bool), n)
+    with pytest.raises(ValueError):
+        cfpq.vertex_mask(np.zeros(2, dtype=np.uint64), n)
+
+
+def test_unknown_graph_flag_rejected():
+    with pytest.raises(cfpq.CfpqError) as e:
+        cfpq.cfpq_graph_create(3, 1, [0], [0], [1], flags=4)
+    assert e.value.status == cfpq.ERR_INVALID
