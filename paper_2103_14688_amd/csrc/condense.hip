@@ -358,131 +358,358 @@ __device__ __forceinline__ uint64_t *comp_row(uint32_t c, uint32_t n, uint32_t P
     return R + (uint64_t)c * P;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, uint32_t Pn, const uint32_t *scc,
+constexpr uint32_t kCondPredCap = 8;     // predecessor rows listed per node; more take the whole-wave path
+// lanes per node when OR-ing rows (kWave / kCondGroupLanes nodes at a time);
+// a compile-time tuning parameter
+#ifndef CFPQ_COND_GROUP_LANES
+#define CFPQ_COND_GROUP_LANES 64
+#endif
+constexpr int kCondGroupLanes = CFPQ_COND_GROUP_LANES;
+static_assert(kWave % kCondGroupLanes == 0 && kCondGroupLanes >= 16, "whole groups of at least 16 lanes");
+constexpr int kCondGroupWords = (int)kCondChunkWords / kCondGroupLanes;
+// words per lane and pass of the OR loop (register budget)
+constexpr int kCondPassWords = kCondGroupWords < 16 ? kCondGroupWords : 16;
+constexpr int kCondPasses = kCondGroupWords / kCondPassWords;
+static_assert(kCondNodes == (uint32_t)kWave, "one node per lane in the edge-parallel phases");
+
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src, kWave); }
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+    return (uint64_t)shfl_u32((uint32_t)x, src) | ((uint64_t)shfl_u32((uint32_t)(x >> 32), src) << 32);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = __lane_id();
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t y = (uint32_t)__shfl_xor((int)x, off, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// word offset of component c's row: in R, or (bit 63 set) in the answer
+// matrix for an aliased answer row (see comp_row)
+__device__ __forceinline__ uint64_t comp_off(uint32_t c, uint32_t n, uint32_t P, const uint32_t *flags,
+                                             const uint32_t *multi) {
+    const uint32_t f = flags[c / n];
+    if ((f & kAliasFinal) && multi[c] == 0) return (1ull << 63) | (((uint64_t)(f >> kFlagBoxShift) * n + (c % n)) * P);
+    return (uint64_t)c * P;
+}
+__device__ __forceinline__ uint64_t *off_ptr(uint64_t o, uint64_t *R, uint64_t *NT) {
+    return (o >> 63) ? NT + (o & ~(1ull << 63)) : R + o;
+}
+
+// Edge-parallel walk over the edges of transition k of every lane's node
+// (lane j owns node j of the work item; b/e/sb: its edge range and the base
+// index of the transition's source (or target) state).  fn(j, e, sb_j, c_j)
+// runs once per edge, 64 edges at a time whatever their owners' degrees.
+template <class F>
+__device__ __forceinline__ void edge_walk(uint32_t *scan, uint32_t b, uint32_t e, uint32_t sb, uint32_t cm, F &&fn) {
+    const int lane = __lane_id();
+    const uint32_t incl = wave_incl_scan(e - b);
+    const uint32_t total = shfl_u32(incl, kWave - 1);
+    if (total == 0) return;
+    scan[lane] = incl;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t f0 = 0; f0 < total; f0 += kWave) {
+        const uint32_t f = f0 + (uint32_t)lane;
+        uint32_t lo = 0, hi = kWave - 1;   // owner: first node whose inclusive count exceeds f
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (scan[mid] > f) hi = mid;
+            else lo = mid + 1;
+        }
+        const uint32_t bj = shfl_u32(b, (int)lo), sbj = shfl_u32(sb, (int)lo), cj = shfl_u32(cm, (int)lo);
+        const uint32_t startj = lo ? scan[lo - 1] : 0u;
+        if (f < total) fn(lo, bj + (f - startj), sbj, cj);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// One node with the whole wavefront: OR the chunk of every predecessor row,
+// add the seed bit, write (nodes with more than kCondPredCap listed rows).
+__device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc,
+                                const uint32_t *multi, uint64_t *R, uint64_t *NT, uint8_t *nz, const uint32_t *flags,
+                                uint32_t p, uint32_t c, uint32_t ch, uint32_t nch,
+                                unsigned long long *box_pairs, unsigned long long &pairs0,
+                                unsigned long long &words_w, unsigned long long &words_r) {
+    const int lane = __lane_id();
+    const uint32_t pass0 = ch * kCondChunkWords;
+    const uint32_t cw = (Pn - pass0 < kCondChunkWords) ? Pn - pass0 : kCondChunkWords;
+    const bool single = multi[c] == 0;
+    const uint32_t q = p / g.n, v = p - q * g.n;
+    const uint32_t fq = flags[q];
+    const bool alias = single && (fq & kAliasFinal);
+    uint64_t *row = comp_row(c, g.n, P, flags, multi, R, NT) + pass0;
+    const uint64_t seed_word =
+        (single && (fq & kStartState) && (!g.src_mask || mask_bit(g.src_mask, v))) ? 1ull << (v & 63) : 0ull;
+    const uint32_t seed_w = v >> 6;
+    uint64_t acc[kCondChunks];
+#pragma unroll
+    for (int k = 0; k < kCondChunks; ++k) acc[k] = 0;
+    uint32_t last = 0xFFFFFFFFu;
+    for (uint32_t t = g.in_off[q]; t < g.in_off[q + 1]; ++t) {
+        const InTrans tr = g.in_tr[t];
+        const uint32_t *o = g.goff + (uint64_t)tr.sym * (g.n + 1) + v;
+        const uint32_t b = o[0], e = o[1], sb = tr.src * g.n;
+        for (uint32_t e0 = b; e0 < e; e0 += kWave) {
+            uint32_t cx = c;
+            bool use = false;
+            if (e0 + lane < e) {
+                cx = scc[sb + g.gidx[e0 + lane]];
+                use = cx != c && nz[(uint64_t)cx * nch + ch];  // empty chunks hold no bits
+            }
+            uint64_t m = __ballot(use);
+            while (m) {
+                const int i = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                const uint32_t ci = (uint32_t)__builtin_amdgcn_readlane((int)cx, i);
+                if (ci == last) continue;  // same row as the one just OR-ed
+                last = ci;
+                if (lane == 0) words_r += cw;
+                const uint64_t *src = comp_row(ci, g.n, P, flags, multi, R, NT) + pass0;
+#pragma unroll
+                for (int k = 0; k < kCondChunks; ++k) {
+                    const uint32_t w = pass0 + k * kWave + lane;
+                    if (w < Pn) acc[k] |= src[k * kWave + lane];
+                }
+            }
+        }
+    }
+    bool nonzero = false;
+#pragma unroll
+    for (int k = 0; k < kCondChunks; ++k) {
+        const uint32_t w = pass0 + k * kWave + lane;
+        if (w == seed_w) acc[k] |= seed_word;
+        nonzero |= acc[k] != 0;
+    }
+    // a chunk that stays empty is neither written nor read later -- except
+    // in an answer row, which must be complete
+    const bool any_bits = __ballot(nonzero) != 0;
+    if (any_bits || alias) {
+        unsigned long long pc = 0;
+#pragma unroll
+        for (int k = 0; k < kCondChunks; ++k) {
+            const uint32_t w = pass0 + k * kWave + lane;
+            if (w < Pn) {
+                if (single)
+                    row[k * kWave + lane] = acc[k];
+                else if (acc[k])
+                    atomicOr((unsigned long long *)&row[k * kWave + lane], acc[k]);
+                if (alias) pc += (unsigned long long)__popcll(acc[k]);
+            }
+        }
+        if (alias) {
+            const uint32_t box = fq >> kFlagBoxShift;
+            if (box == 0) pairs0 += pc;
+            else if (pc) atomicAdd(&box_pairs[box * kWave], pc);
+        }
+        if (lane == 0) {
+            if (any_bits) nz[(uint64_t)c * nch + ch] = 1;
+            words_w += cw;
+        }
+    }
+}
+
+// One topological level L of the component graph: every component whose
+// predecessors are all done gets its row (per 512-word chunk) as the OR of
+// its predecessors' rows plus its seed bit, then releases its successors.
+// A work item is 64 consecutive product nodes (one per lane) and one chunk:
+//   A. edge-parallel over the items' in-edges: predecessor components with a
+//      non-empty chunk go to a short LDS list per node (with their row
+//      offsets, so the OR loop issues nothing but row loads);
+//   B. four nodes at a time, 16 lanes each, OR their listed rows (32 words
+//      per lane in flight) and write the chunk; nodes with longer lists take
+//      the whole-wavefront path;
+//   C. (first chunk only) edge-parallel over the out-edges: retire the
+//      in-degree stripes of successor components and release them into
+//      level L + 1.
+#ifndef CFPQ_COND_MIN_WAVES
+#define CFPQ_COND_MIN_WAVES 1
+#endif
+__global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(ProdGraph g, uint32_t P, uint32_t Pn, const uint32_t *scc,
                                                        const uint32_t *multi, uint32_t *indeg, uint32_t *pending,
                                                        uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
                                                        const uint32_t *flags, uint32_t L,
                                                        const unsigned long long *ctr_prev,
                                                        unsigned long long *ctr_next, unsigned long long *ctr_clear,
                                                        unsigned long long *box_pairs, unsigned long long *bytes_ctr) {
+    __shared__ uint64_t s_pred[kBlock / kWave][kCondNodes][kCondPredCap];
+    __shared__ uint32_t s_cnt[kBlock / kWave][kCondNodes];
+    __shared__ uint32_t s_scan[kBlock / kWave][kCondNodes];
     if (blockIdx.x == 0 && threadIdx.x == 0) *ctr_clear = 0;  // the counter level L + 2 will write
     if (*ctr_prev == 0) return;  // nothing reached level L
     const uint32_t N = g.nQ * g.n;
     const int lane = __lane_id();
+    const uint32_t wib = threadIdx.x / kWave;
+    const int grp = lane / kCondGroupLanes, gl = lane % kCondGroupLanes;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
+    const uint32_t nch = (Pn + kCondChunkWords - 1) / kCondChunkWords;
     const uint64_t items = (((uint64_t)N + kCondNodes - 1) / kCondNodes) * nch;
     unsigned long long released = 0, pairs0 = 0, words_w = 0, words_r = 0;
     for (uint64_t it = wave; it < items; it += nwaves) {
         const uint64_t base = (it / nch) * kCondNodes;
         const uint32_t ch = (uint32_t)(it % nch);
-        const uint32_t pass0 = ch * (kCondChunks * kWave);
-        const uint32_t cw = (Pn - pass0 < kCondChunks * kWave) ? Pn - pass0 : kCondChunks * kWave;  // words in chunk
+        const uint32_t pass0 = ch * kCondChunkWords;
+        const uint32_t cw = (Pn - pass0 < kCondChunkWords) ? Pn - pass0 : kCondChunkWords;  // words in chunk
         const uint32_t mine = (uint32_t)(base + lane);
         uint32_t cm = 0;
         bool at = false;
-        if ((uint32_t)lane < kCondNodes && mine < N) {
+        if (mine < N) {
             cm = scc[mine];
             at = lev[cm] == L;
         }
-        uint64_t todo = __ballot(at);
-        while (todo) {
-            const int j = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            const uint32_t p = (uint32_t)base + (uint32_t)j;
-            const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cm, j);
-            const bool single = multi[c] == 0;
-            const uint32_t q = p / g.n, v = p - q * g.n;
-            const uint32_t fq = flags[q];
-            const bool alias = single && (fq & kAliasFinal);
-            uint64_t *row = comp_row(c, g.n, P, flags, multi, R, NT) + pass0;
-            // seed bit of a single-member component: (start, v) is where source v begins
-            const uint64_t seed_word =
-                (single && (fq & kStartState) && (!g.src_mask || mask_bit(g.src_mask, v))) ? 1ull << (v & 63) : 0ull;
-            const uint32_t seed_w = v >> 6;
-            uint64_t acc[kCondChunks];
-#pragma unroll
-            for (int k = 0; k < kCondChunks; ++k) acc[k] = 0;
-            uint32_t last = 0xFFFFFFFFu;
-            for (uint32_t t = g.in_off[q]; t < g.in_off[q + 1]; ++t) {
-                const InTrans tr = g.in_tr[t];
+        const uint64_t todo = __ballot(at);
+        if (!todo) continue;
+        // node metadata (lane j: node base + j)
+        uint32_t q = 0, v = 0, fq = 0, tb = 0, te = 0, single = 0;
+        uint64_t own = 0;
+        if (at) {
+            q = mine / g.n;
+            v = mine - q * g.n;
+            fq = flags[q];
+            single = multi[cm] == 0;
+            own = comp_off(cm, g.n, P, flags, multi);
+            tb = g.in_off[q];
+            te = g.in_off[q + 1];
+        }
+        // A. listed predecessor rows
+        s_cnt[wib][lane] = 0;
+        const uint32_t ntr = wave_max_u32(te - tb);
+        for (uint32_t k = 0; k < ntr; ++k) {
+            uint32_t b = 0, e = 0, sb = 0;
+            if (tb + k < te) {
+                const InTrans tr = g.in_tr[tb + k];
                 const uint32_t *o = g.goff + (uint64_t)tr.sym * (g.n + 1) + v;
-                const uint32_t b = o[0], e = o[1], sb = tr.src * g.n;
-                for (uint32_t e0 = b; e0 < e; e0 += kWave) {
-                    uint32_t cx = c;
-                    bool use = false;
-                    if (e0 + lane < e) {
-                        cx = scc[sb + g.gidx[e0 + lane]];
-                        use = cx != c && nz[(uint64_t)cx * nch + ch];  // empty chunks hold no bits
-                    }
-                    uint64_t m = __ballot(use);
-                    while (m) {
-                        const int i = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        const uint32_t ci = (uint32_t)__builtin_amdgcn_readlane((int)cx, i);
-                        if (ci == last) continue;  // same row as the one just OR-ed
-                        last = ci;
-                        words_r += cw;
-                        const uint64_t *src = comp_row(ci, g.n, P, flags, multi, R, NT) + pass0;
+                b = o[0];
+                e = o[1];
+                sb = tr.src * g.n;
+            }
+            edge_walk(s_scan[wib], b, e, sb, cm, [&](uint32_t j, uint32_t ei, uint32_t sbj, uint32_t cj) {
+                const uint32_t cx = scc[sbj + g.gidx[ei]];
+                if (cx == cj || !nz[(uint64_t)cx * nch + ch]) return;
+                const uint64_t off = comp_off(cx, g.n, P, flags, multi);
+                const uint32_t have = s_cnt[wib][j];
+                for (uint32_t r = 0; r < have && r < kCondPredCap; ++r)
+                    if (s_pred[wib][j][r] == off) return;   // listed already
+                const uint32_t slot = atomicAdd(&s_cnt[wib][j], 1u);
+                if (slot < kCondPredCap) s_pred[wib][j][slot] = off;
+            });
+        }
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t my_cnt = s_cnt[wib][lane];
+        const uint64_t over = __ballot(at && my_cnt > kCondPredCap);
+        // B. four nodes at a time
+        uint64_t pend = todo & ~over;
+        while (pend) {
+            int jg = -1;
 #pragma unroll
-                        for (int k = 0; k < kCondChunks; ++k) {
-                            const uint32_t w = pass0 + k * kWave + lane;
-                            if (w < Pn) acc[k] |= src[k * kWave + lane];
-                        }
+            for (int gi = 0; gi < kWave / kCondGroupLanes; ++gi) {
+                if (pend) {
+                    const int j = __ffsll((unsigned long long)pend) - 1;
+                    pend &= pend - 1;
+                    if (grp == gi) jg = j;
+                }
+            }
+            const int js = jg < 0 ? 0 : jg;
+            const uint32_t cj = shfl_u32(cm, js), vj = shfl_u32(v, js), fqj = shfl_u32(fq, js);
+            const uint32_t cntj = shfl_u32(my_cnt, js), singlej = shfl_u32(single, js);
+            const uint64_t ownj = shfl_u64(own, js);
+            if (jg < 0) continue;
+            const bool seeded = singlej && (fqj & kStartState) && (!g.src_mask || mask_bit(g.src_mask, vj));
+            const uint32_t sw = vj >> 6;   // the seed: source vj begins at (start, vj)
+            const bool seed_here = seeded && sw >= pass0 && sw < pass0 + cw;
+            // every listed row has a non-empty chunk (its flag says so), so the
+            // chunk is non-empty iff something is listed or the seed is in it
+            const bool any_bits = cntj > 0 || seed_here;
+            const bool alias = singlej && (fqj & kAliasFinal);
+            if (!any_bits && !alias) continue;   // an empty chunk is neither written nor read later
+            uint64_t *row = off_ptr(ownj, R, NT) + pass0;
+            unsigned long long pc = 0;
+#pragma unroll
+            for (int h = 0; h < kCondPasses; ++h) {
+                constexpr int kH = kCondPassWords;
+                const uint32_t hw0 = (uint32_t)(h * kH * kCondGroupLanes);
+                uint64_t acc[kH];
+#pragma unroll
+                for (int kk = 0; kk < kH; ++kk) acc[kk] = 0;
+                for (uint32_t k = 0; k < cntj; ++k) {
+                    const uint64_t *src = off_ptr(s_pred[wib][jg][k], R, NT) + pass0 + hw0;
+#pragma unroll
+                    for (int kk = 0; kk < kH; ++kk) {
+                        const uint32_t w = hw0 + (uint32_t)(kk * kCondGroupLanes + gl);
+                        if (w < cw) acc[kk] |= src[kk * kCondGroupLanes + gl];
+                    }
+                }
+                if (seed_here) {
+#pragma unroll
+                    for (int kk = 0; kk < kH; ++kk)
+                        if (hw0 + (uint32_t)(kk * kCondGroupLanes + gl) == sw - pass0) acc[kk] |= 1ull << (vj & 63);
+                }
+#pragma unroll
+                for (int kk = 0; kk < kH; ++kk) {
+                    const uint32_t w = hw0 + (uint32_t)(kk * kCondGroupLanes + gl);
+                    if (w < cw) {
+                        if (singlej)
+                            row[w] = acc[kk];
+                        else if (acc[kk])
+                            atomicOr((unsigned long long *)&row[w], acc[kk]);
+                        if (alias) pc += (unsigned long long)__popcll(acc[kk]);
                     }
                 }
             }
-            bool nonzero = false;
-#pragma unroll
-            for (int k = 0; k < kCondChunks; ++k) {
-                const uint32_t w = pass0 + k * kWave + lane;
-                if (w == seed_w) acc[k] |= seed_word;
-                nonzero |= acc[k] != 0;
+            if (alias) {
+                const uint32_t box = fqj >> kFlagBoxShift;
+                if (box == 0) pairs0 += pc;
+                else if (pc) atomicAdd(&box_pairs[box * kWave], pc);
             }
-            // a chunk that stays empty is neither written nor read later --
-            // except in an answer row, which must be complete
-            const bool any_bits = __ballot(nonzero) != 0;
-            if (any_bits || alias) {
-#pragma unroll
-                for (int k = 0; k < kCondChunks; ++k) {
-                    const uint32_t w = pass0 + k * kWave + lane;
-                    if (w < Pn) {
-                        if (single)
-                            row[k * kWave + lane] = acc[k];
-                        else if (acc[k])
-                            atomicOr((unsigned long long *)&row[k * kWave + lane], acc[k]);
-                        if (alias) pairs0 += (unsigned long long)__popcll(acc[k]);
-                    }
-                }
-                if (lane == 0 && any_bits) nz[(uint64_t)c * nch + ch] = 1;
+            if (gl == 0) {
+                if (any_bits) nz[(uint64_t)cj * nch + ch] = 1;
                 words_w += cw;
+                words_r += (unsigned long long)cntj * cw;
             }
-            if (alias && (fq >> kFlagBoxShift) != 0) {
-                // answer pairs of a box other than 0: count directly
-                unsigned long long t = wsum(pairs0);
-                if (lane == 0 && t) atomicAdd(&box_pairs[(fq >> kFlagBoxShift) * kWave], t);
-                pairs0 = 0;
+        }
+        for (uint64_t ov = over; ov;) {
+            const int j = __ffsll((unsigned long long)ov) - 1;
+            ov &= ov - 1;
+            level_node_wave(g, P, Pn, scc, multi, R, NT, nz, flags, (uint32_t)base + (uint32_t)j,
+                            (uint32_t)__builtin_amdgcn_readlane((int)cm, j), ch, nch, box_pairs, pairs0, words_w,
+                            words_r);
+        }
+        // C. release successor components (once per node: first chunk)
+        if (ch == 0) {
+            uint32_t ob = 0, oe = 0;
+            if (at) {
+                ob = g.out_off[q];
+                oe = g.out_off[q + 1];
             }
-            if (pass0 == 0) {
-                // release successor components, lane-parallel
-                for (uint32_t t = g.out_off[q]; t < g.out_off[q + 1]; ++t) {
-                    const InTrans tr = g.out_tr[t];
+            const uint32_t nout = wave_max_u32(oe - ob);
+            for (uint32_t k = 0; k < nout; ++k) {
+                uint32_t b = 0, e = 0, sb = 0;
+                if (ob + k < oe) {
+                    const InTrans tr = g.out_tr[ob + k];   // src field: destination state
                     const uint32_t *o = g.soff + (uint64_t)tr.sym * (g.n + 1) + v;
-                    const uint32_t b = o[0], e = o[1], sb = tr.src * g.n;
-                    for (uint32_t e0 = b; e0 < e; e0 += kWave) {
-                        if (e0 + lane < e) {
-                            const uint32_t cx = scc[sb + g.sidx[e0 + lane]];
-                            // the last edge of a stripe retires the stripe, the
-                            // last stripe releases the component
-                            if (cx != c && atomicSub(&indeg[(uint64_t)cx * kStripes + p % kStripes], 1u) == 1u &&
-                                atomicSub(&pending[cx], 1u) == 1u) {
-                                lev[cx] = L + 1;
-                                ++released;
-                            }
-                        }
-                    }
+                    b = o[0];
+                    e = o[1];
+                    sb = tr.src * g.n;
                 }
+                edge_walk(s_scan[wib], b, e, sb, cm, [&](uint32_t j, uint32_t ei, uint32_t sbj, uint32_t cj) {
+                    const uint32_t cx = scc[sbj + g.sidx[ei]];
+                    const uint32_t pj = (uint32_t)base + j;
+                    // the last edge of a stripe retires the stripe, the last
+                    // stripe releases the component
+                    if (cx != cj && atomicSub(&indeg[(uint64_t)cx * kStripes + pj % kStripes], 1u) == 1u &&
+                        atomicSub(&pending[cx], 1u) == 1u) {
+                        lev[cx] = L + 1;
+                        ++released;
+                    }
+                });
             }
         }
     }
@@ -493,9 +720,13 @@ __global__ __launch_bounds__(kBlock) void k_cond_level(ProdGraph g, uint32_t P, 
     if (lane == 0 && pairs0) atomicAdd(&box_pairs[wave % kWave], pairs0);
     // words written and predecessor words requested (profiling only), striped
     // over kWave counter pairs
-    if (bytes_ctr && lane == 0 && (words_w | words_r)) {
-        atomicAdd(&bytes_ctr[2 * (wave % kWave)], words_w);
-        atomicAdd(&bytes_ctr[2 * (wave % kWave) + 1], words_r);
+    if (bytes_ctr) {
+        words_w = wsum(words_w);
+        words_r = wsum(words_r);
+        if (lane == 0 && (words_w | words_r)) {
+            atomicAdd(&bytes_ctr[2 * (wave % kWave)], words_w);
+            atomicAdd(&bytes_ctr[2 * (wave % kWave) + 1], words_r);
+        }
     }
 }
 
