@@ -1619,4 +1619,4 @@ extern "C" void cfpq_result_destroy(cfpq_result r) { delete r; }
 
 extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
 
-extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.2"; }
+extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.3"; }
