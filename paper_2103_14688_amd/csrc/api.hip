@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cstdio>
 #include <cstring>
@@ -107,6 +108,10 @@ struct cfpq_graph_s {
     DevBuf off, idx;                         // CSC per label (predecessors)
     DevBuf soff, sidx;                       // CSR per label (successors)
     std::vector<uint32_t> h_out_off, h_out;  // CSR per label (successors), host
+    // launch-chain sizes the last condensed query on this graph needed
+    // (speculation only: a chain that needs more continues, one that needs
+    // less exits its surplus launches at once)
+    mutable std::atomic<uint32_t> hint_trim{0}, hint_reach{0}, hint_levels{0};
 };
 
 struct cfpq_rsm_s {
@@ -841,7 +846,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     const bool nullable = !p.eps_boxes.empty();
     if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, nullable ? bw * 8 : 8, s) ||
         !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) || !u32s.alloc(al, Nu * 4 * (8 + kStripes) + 64, s) ||
-        !u8s.alloc(al, 2 * N64 + nzb + 64, s) || !ctr.alloc(al, (uint64_t)2 * kCtr * 8, s))
+        !u8s.alloc(al, 2 * N64 + nzb + 64, s) || !ctr.alloc(al, ((uint64_t)2 * kCtr + 8) * 8, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (condensed query)");
     if (o.keep_rank) {
         if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
@@ -890,7 +895,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     // run launch(i, prev, cur) as a chain until a launch counts zero: chunks of
     // launches go out back to back, each exits at once when its predecessor
     // counted zero, and the host reads the chunk's counters once
-    auto chain = [&](auto launch, uint32_t chunk) -> cfpq_status {
+    auto chain = [&](auto launch, uint32_t chunk, std::atomic<uint32_t> *used) -> cfpq_status {
         const unsigned long long *prev = nullptr;
         for (uint32_t i = 0;;) {
             if (slot + chunk >= kCtr) {
@@ -908,7 +913,10 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             cfpq_status st2 = read(first, chunk);
             if (st2 != CFPQ_OK) return st2;
             for (uint32_t j = 0; j < chunk; ++j)
-                if (pc.h[j] == 0) return CFPQ_OK;
+                if (pc.h[j] == 0) {
+                    if (used) used->store(i - chunk + j + 1, std::memory_order_relaxed);
+                    return CFPQ_OK;
+                }
             chunk = std::min<uint32_t>(chunk * 2, 256);
         }
     };
@@ -917,7 +925,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     // M2^N is empty unless a box is nullable; then it needs the epsilon loops
     const bool fresh = p.eps_boxes.empty();
     if (!fresh) HIP_TRY(launch_fill(d_u64(res.NT), bw, 0, s));
-    HIP_TRY(launch_fill((uint64_t *)cc, 2 * kCtr, 0, s));
+    HIP_TRY(launch_fill((uint64_t *)cc, 2 * kCtr + 8, 0, s));
     HIP_TRY(launch_fill((uint64_t *)u32s.p, (Nu * 4 * (8 + kStripes) + 64) / 8, 0, s));
     HIP_TRY(launch_fill((uint64_t *)alive, N64 / 8, 0x0101010101010101ull, s));  // every node live
     HIP_TRY(launch_fill((uint64_t *)found, (N64 + nzb) / 8 + 8, 0, s));   // found, non-empty flags := 0
@@ -930,27 +938,28 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
 
     // ---- strongly connected components of the product graph
     // trimming: nodes with no live predecessor or successor
+    auto chunk0 = [](const std::atomic<uint32_t> &h, uint32_t dflt) {
+        const uint32_t v = h.load(std::memory_order_relaxed);
+        return v ? std::min<uint32_t>(v, 256) : dflt;
+    };
     st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
         return launch_trim(pg, alive, scc, pv, c, s);
-    }, 8);
+    }, chunk0(g.hint_trim, 8), &g.hint_trim);
     if (st != CFPQ_OK) return st;
-    // the component of a high-degree pivot: forward AND backward reachable
+    // the component of a high-degree pivot: forward AND backward reachable;
+    // the pivot goes from k_pivot to the searches on the device
     {
+        // the pivot key lives past the launch counters, which a long chain
+        // clears and reuses
+        unsigned long long *best = cc + 2 * kCtr;
+        HIP_TRY(launch_pivot(pg, alive, best, s));
+        HIP_TRY(launch_pivot_seed(best, fw, bwm, s));
+        st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
+            return launch_reach(pg, alive, fw, bwm, pv, c, s);
+        }, chunk0(g.hint_reach, 8), &g.hint_reach);
+        if (st != CFPQ_OK) return st;
         if ((st = next_slot(1)) != CFPQ_OK) return st;
-        const uint32_t best_slot = slot++;
-        HIP_TRY(launch_pivot(pg, alive, cc + best_slot, s));
-        if ((st = read(best_slot, 1)) != CFPQ_OK) return st;
-        if (pc.h[0]) {
-            const uint32_t pivot = (uint32_t)(pc.h[0] & 0xFFFFFFFFull);
-            HIP_TRY(launch_set_u32(fw, pivot, 1, s));
-            HIP_TRY(launch_set_u32(bwm, pivot, 1, s));
-            st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
-                return launch_reach(pg, alive, fw, bwm, pv, c, s);
-            }, 8);
-            if (st != CFPQ_OK) return st;
-            if ((st = next_slot(1)) != CFPQ_OK) return st;
-            HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, pivot, scc, cc + slot++, s));
-        }
+        HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, best, scc, cc + slot++, s));
     }
     // colouring rounds for the rest
     for (;;) {
@@ -962,12 +971,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         HIP_TRY(launch_color_init(N, alive, color, found, s));
         st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
             return launch_color_prop(pg, alive, color, pv, c, s);
-        }, 8);
+        }, 8, nullptr);
         if (st != CFPQ_OK) return st;
         HIP_TRY(launch_color_roots(N, alive, color, found, scc, s));
         st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
             return launch_color_back(pg, alive, color, found, scc, pv, c, s);
-        }, 8);
+        }, 8, nullptr);
         if (st != CFPQ_OK) return st;
     }
     HIP_TRY(hipEventRecord(ev[1], s));
@@ -979,7 +988,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     // level L's component count lives in lc[L % kCtr]; the launch for level L
     // clears lc[(L + 2) % kCtr] before level L + 1 writes it
     HIP_TRY(launch_cond_roots(N, scc, stripe, pending, lev, lc + 0, s));
-    uint32_t L = 0, hint = 32;
+    uint32_t L = 0, hint = chunk0(g.hint_levels, 32);
     uint64_t comps = 0;
     // answer pairs counted by the closure: kWave stripes per box
     if ((uint64_t)nB * (kWave + kSlotWords) > kBytesSlot)
@@ -1024,6 +1033,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             const unsigned long long c = pc.h[(L + j) % kCtr];
             if (c == 0) {
                 done = true;
+                g.hint_levels.store(std::max<uint32_t>(L + j, 1), std::memory_order_relaxed);
                 break;
             }
             comps += (j < k) ? c : 0;

@@ -154,36 +154,21 @@ __global__ void k_reach(ProdGraph g, const uint8_t *alive, uint32_t *fw, uint32_
     count_add(ctr, c);
 }
 
-__global__ void k_set_u32(uint32_t *a, uint32_t i, uint32_t v) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) a[i] = v;
-}
-
-// one level of a push breadth-first search restricted to live nodes: every
-// node of the input frontier marks its unmarked live successors (forward) or
-// predecessors (backward) and appends them to the output frontier
-__global__ void k_push(ProdGraph g, const uint8_t *alive, uint32_t *mark, int backward, const uint32_t *fin,
-                       const unsigned long long *n_in, uint32_t *fout, unsigned long long *n_out) {
-    const unsigned long long cnt = *n_in;
-    if (cnt == 0) return;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = fin[i];
-        auto f = [&](uint32_t x) {
-            if (alive[x] && mark[x] == 0 && atomicExch(&mark[x], 1u) == 0u) {
-                const unsigned long long at = atomicAdd(n_out, 1ull);
-                fout[at] = x;
-            }
-            return true;
-        };
-        if (backward) for_preds(g, p, f); else for_succs(g, p, f);
-    }
-}
-
-__global__ void k_set_u64(unsigned long long *a, unsigned long long v) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a = v;
+// the pivot (from k_pivot's best key) starts both searches
+__global__ void k_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const unsigned long long b = *best;
+    if (!b) return;
+    const uint32_t p = (uint32_t)(b & 0xFFFFFFFFull);
+    fw[p] = 1;
+    bw[p] = 1;
 }
 
 __global__ void k_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
-                              uint32_t pivot, uint32_t *scc, unsigned long long *ctr) {
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr) {
+    const unsigned long long b = *best;
+    if (!b) return;
+    const uint32_t pivot = (uint32_t)(b & 0xFFFFFFFFull);
     unsigned long long c = 0;
     NODE_LOOP(N) {
         if (alive[p] && fw[p] && bw[p]) {
@@ -779,26 +764,14 @@ hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, 
     return hipGetLastError();
 }
 
-hipError_t launch_push(const ProdGraph &g, const uint8_t *alive, uint32_t *mark, int backward, const uint32_t *fin,
-                       const unsigned long long *n_in, uint32_t *fout, unsigned long long *n_out, uint32_t grid,
-                       hipStream_t s) {
-    hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, s, g, alive, mark, backward, fin, n_in, fout, n_out);
+hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, hipStream_t s) {
+    hipLaunchKernelGGL(k_pivot_seed, dim3(1), dim3(64), 0, s, best, fw, bw);
     return hipGetLastError();
 }
 
-hipError_t launch_set_u64(unsigned long long *a, unsigned long long v, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, a, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_set_u32(uint32_t *a, uint32_t i, uint32_t v, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, a, i, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw, uint32_t pivot,
-                              uint32_t *scc, unsigned long long *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwbw_assign, dim3(node_grid(N)), dim3(kBlock), 0, s, N, alive, fw, bw, pivot, scc, ctr);
+hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwbw_assign, dim3(node_grid(N)), dim3(kBlock), 0, s, N, alive, fw, bw, best, scc, ctr);
     return hipGetLastError();
 }
 

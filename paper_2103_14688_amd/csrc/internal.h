@@ -151,13 +151,11 @@ struct ProdGraph {
 hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
                        unsigned long long *ctr, hipStream_t s);
 hipError_t launch_pivot(const ProdGraph &g, const uint8_t *alive, unsigned long long *best, hipStream_t s);
+// one sweep of forward/backward reachability from the pivot (marks in place)
 hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
                         const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
-hipError_t launch_set_u32(uint32_t *a, uint32_t i, uint32_t v, hipStream_t s);
-hipError_t launch_set_u64(unsigned long long *a, unsigned long long v, hipStream_t s);
-hipError_t launch_push(const ProdGraph &g, const uint8_t *alive, uint32_t *mark, int backward, const uint32_t *fin,
-                       const unsigned long long *n_in, uint32_t *fout, unsigned long long *n_out, uint32_t grid,
-                       hipStream_t s);
+// the pivot in *best (k_pivot's key; 0 = none) starts both searches
+hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, hipStream_t s);
 constexpr uint32_t kStripes = 16;           // in-degree counters per component
 // per-state flags of the condensed strategy: bit 0 box start, bit 1 the only
 // final state of its box (its single-member rows alias the answer), box id
@@ -166,8 +164,8 @@ constexpr uint32_t kStartState = 1, kAliasFinal = 2, kFlagBoxShift = 2;
 // counters of the condensed levels: kWave stripes of answer pairs per box,
 // then (at kBytesSlot) kWave (words written, predecessor words requested) pairs
 constexpr uint32_t kBytesSlot = 4096;
-hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw, uint32_t pivot,
-                              uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_init(uint32_t N, const uint8_t *alive, uint32_t *color, uint8_t *found, hipStream_t s);
 hipError_t launch_color_prop(const ProdGraph &g, const uint8_t *alive, uint32_t *color,
                              const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
