@@ -46,10 +46,11 @@ def main():
     ap.add_argument("--nt-mode", choices=["auto", "rows", "mfma"], default="auto",
                     help="box-labelled transitions in closure levels (grammar workloads): automatic, "
                          "whole-row OR, or the int8 matrix-core product")
-    ap.add_argument("--cpu-sources", type=int, default=4000, help="oracle sample size (sources)")
+    ap.add_argument("--cpu-sources", type=int, default=20000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400)
     ap.add_argument("--serve-nmax", type=int, default=20000)
+    ap.add_argument("--serve-slots", type=int, default=8, help="execution slots (streams) of the batched server")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--workload", choices=["rpq", "brackets", "samegen", "alias"], default="rpq",
                     help="rpq (default, the headline) or one of the other measured workloads")
@@ -272,9 +273,9 @@ def measure_serving(args):
     """Batched vs plain on the serving mix: 64 resident power-law graphs
     (n log-uniform in [1000, serve_nmax], mean out-degree 3, 8 Zipf labels),
     random regex / normal-form grammar queries.  Closed loop (all requests at
-    t = 0) gives throughput; an open loop with Poisson arrivals at 0.7x the
-    plain throughput gives p50/p99 latency.  Every batched answer is compared
-    with the plain one (count, hash, iterations)."""
+    t = 0) gives throughput; open loops with Poisson arrivals at 0.5, 1, 2 and
+    4 times the plain throughput give p50/p99 latency.  Every batched answer
+    is compared with the plain one (count, hash, iterations)."""
     import numpy as np
 
     import synth
@@ -296,7 +297,7 @@ def measure_serving(args):
     backend = serve.GpuBackend()
 
     def run(mode, arrivals=None):
-        srv = serve.Server(backend, mode=mode, slots=4)
+        srv = serve.Server(backend, mode=mode, slots=args.serve_slots)
         rs = requests()
         t0 = time.perf_counter()
         if arrivals is None:
@@ -318,27 +319,33 @@ def measure_serving(args):
     same = all(a.result == b.result for a, b in zip(plain, batched))
     pairs = sum(r.result[0] for r in plain)
     mu = len(plain) / wall_p
-    lam = 0.7 * mu
-    arr = np.cumsum(np.random.default_rng(synth.BASE_SEED + 9).exponential(1.0 / lam, size=len(comp)))
-    plain_o, _, _ = run("plain", arr)
-    batched_o, _, _ = run("batched", arr)
-    pp = serve.percentiles([r.latency for r in plain_o])
-    pb = serve.percentiles([r.latency for r in batched_o])
+    same_open = True
+    sweep = []
+    for factor in (0.5, 1.0, 2.0, 4.0):
+        lam = factor * mu
+        arr = np.cumsum(np.random.default_rng(synth.BASE_SEED + 9).exponential(1.0 / lam, size=len(comp)))
+        plain_o, _, _ = run("plain", arr)
+        batched_o, _, _ = run("batched", arr)
+        pp = serve.percentiles([r.latency for r in plain_o])
+        pb = serve.percentiles([r.latency for r in batched_o])
+        same_open &= all(a.result == b.result for a, b in zip(plain_o, batched_o))
+        sweep.append({"arrival_rate_per_s": lam, "x_plain_capacity": factor,
+                      "plain_p50_ms": pp[50] * 1e3, "plain_p99_ms": pp[99] * 1e3,
+                      "batched_p50_ms": pb[50] * 1e3, "batched_p99_ms": pb[99] * 1e3})
+        print(f"# serving open loop {factor}x: plain p50/p99 {pp[50] * 1e3:.1f}/{pp[99] * 1e3:.1f} ms, "
+              f"batched {pb[50] * 1e3:.1f}/{pb[99] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     return {
         "workload": f"{len(comp)} queries (half regex, half CFG) on 64 resident power-law graphs, "
                     f"n log-uniform in [1000, {args.serve_nmax}]",
+        "slots": args.serve_slots,
         "closed_loop": {
             "plain_queries_per_s": mu, "batched_queries_per_s": len(batched) / wall_b,
             "plain_pairs_per_s": pairs / wall_p, "batched_pairs_per_s": pairs / wall_b,
             "speedup": wall_p / wall_b, "batched_launch_groups": srv_b.batches,
             "max_concurrent_slots": srv_b.max_concurrent,
         },
-        "open_loop": {
-            "arrival_rate_per_s": lam,
-            "plain_p50_ms": pp[50] * 1e3, "plain_p99_ms": pp[99] * 1e3,
-            "batched_p50_ms": pb[50] * 1e3, "batched_p99_ms": pb[99] * 1e3,
-        },
-        "answers_identical_alone_vs_mix": same and all(a.result == b.result for a, b in zip(plain_o, batched_o)),
+        "open_loop": sweep,
+        "answers_identical_alone_vs_mix": same and same_open,
         "total_pairs": pairs,
     }
 

@@ -337,9 +337,18 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
     unsigned long long *acc = lds_acc + (uint64_t)wib * a.gw;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    // dense rows (more set bits than an ELL list holds) are ORed into
+    // registers, kDenseRegs words per lane (the first kDenseRegs * 64 words
+    // of the tile; the rest through LDS), four rows per step so that their
+    // loads are in flight together
+    constexpr int kDenseRegs = 8;
+    const uint32_t gw_reg = a.gw < kDenseRegs * kWave ? a.gw : kDenseRegs * kWave;
     for (uint64_t r = wave; r < (uint64_t)a.nQ * a.n; r += nwaves) {
         const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
         bool cleared = false, any = false;
+        uint64_t dacc[kDenseRegs];
+#pragma unroll
+        for (int q = 0; q < kDenseRegs; ++q) dacc[q] = 0;
         for (uint32_t t = a.in_off[f]; t < a.in_off[f + 1]; ++t) {
             const InTrans tr = a.in_tr[t];
             if (tr.sym < a.n_terms) continue;
@@ -378,12 +387,25 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                         }
                     }
                     uint64_t dm = __ballot(dense);
+                    const uint64_t *rbase = a.src + ((uint64_t)tr.src * a.n + xb) * a.src_pitch + a.src_off;
                     while (dm) {
-                        const int d = __ffsll((unsigned long long)dm) - 1;
-                        dm &= dm - 1;
-                        const uint64_t *row = a.src + ((uint64_t)tr.src * a.n + xb + (uint32_t)d) * a.src_pitch +
-                                              a.src_off;
-                        for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] |= row[w];
+                        uint32_t d[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            // fewer than four left: repeat the first (OR is idempotent)
+                            d[q] = dm ? (uint32_t)(__ffsll((unsigned long long)dm) - 1) : d[0];
+                            dm &= dm - 1;
+                        }
+                        const uint64_t *r0 = rbase + (uint64_t)d[0] * a.src_pitch;
+                        const uint64_t *r1 = rbase + (uint64_t)d[1] * a.src_pitch;
+                        const uint64_t *r2 = rbase + (uint64_t)d[2] * a.src_pitch;
+                        const uint64_t *r3 = rbase + (uint64_t)d[3] * a.src_pitch;
+#pragma unroll
+                        for (int q = 0; q < kDenseRegs; ++q) {
+                            const uint32_t w = (uint32_t)(q * kWave + lane);
+                            if (w < gw_reg) dacc[q] |= r0[w] | r1[w] | r2[w] | r3[w];
+                        }
+                        for (uint32_t w = gw_reg + lane; w < a.gw; w += kWave) acc[w] |= r0[w] | r1[w] | r2[w] | r3[w];
                     }
                     any = true;
                     __builtin_amdgcn_wave_barrier();
@@ -391,6 +413,12 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             }
         }
         if (!any) continue;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < kDenseRegs; ++q) {
+            const uint32_t w = (uint32_t)(q * kWave + lane);
+            if (w < gw_reg) acc[w] |= dacc[q];
+        }
         __builtin_amdgcn_wave_barrier();
         uint64_t *out = extra + ((uint64_t)f * a.n + v) * a.G;
         bool nz = false;
