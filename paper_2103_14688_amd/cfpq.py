@@ -129,8 +129,15 @@ def torch_allocator():
             except Exception:
                 return None
 
+        cuda = torch.cuda
+
         def _free(ptr, size, stream, ctx):
-            torch.cuda.caching_allocator_delete(ptr)
+            # at interpreter exit torch may already be torn down; the process
+            # releases the memory then anyway
+            try:
+                cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
 
         a = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
         _torch_alloc = a

@@ -339,9 +339,13 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     // dense rows (more set bits than an ELL list holds) are ORed into
     // registers, kDenseRegs words per lane (the first kDenseRegs * 64 words
-    // of the tile; the rest through LDS), four rows per step so that their
-    // loads are in flight together
+    // of the tile; the rest through LDS), kDenseRows rows per step so that
+    // their loads are in flight together
     constexpr int kDenseRegs = 8;
+#ifndef CFPQ_DENSE_ROWS
+#define CFPQ_DENSE_ROWS 2
+#endif
+    constexpr int kDenseRows = CFPQ_DENSE_ROWS;   // rows in flight per step (tuning parameter)
     const uint32_t gw_reg = a.gw < kDenseRegs * kWave ? a.gw : kDenseRegs * kWave;
     for (uint64_t r = wave; r < (uint64_t)a.nQ * a.n; r += nwaves) {
         const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
@@ -389,23 +393,30 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                     uint64_t dm = __ballot(dense);
                     const uint64_t *rbase = a.src + ((uint64_t)tr.src * a.n + xb) * a.src_pitch + a.src_off;
                     while (dm) {
-                        uint32_t d[4];
+                        const uint64_t *rr[kDenseRows];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            // fewer than four left: repeat the first (OR is idempotent)
-                            d[q] = dm ? (uint32_t)(__ffsll((unsigned long long)dm) - 1) : d[0];
+                        for (int q = 0; q < kDenseRows; ++q) {
+                            // fewer rows left: repeat the first (OR is idempotent)
+                            const uint32_t d = dm ? (uint32_t)(__ffsll((unsigned long long)dm) - 1) : 0u;
+                            rr[q] = dm ? rbase + (uint64_t)d * a.src_pitch : rr[0];
                             dm &= dm - 1;
                         }
-                        const uint64_t *r0 = rbase + (uint64_t)d[0] * a.src_pitch;
-                        const uint64_t *r1 = rbase + (uint64_t)d[1] * a.src_pitch;
-                        const uint64_t *r2 = rbase + (uint64_t)d[2] * a.src_pitch;
-                        const uint64_t *r3 = rbase + (uint64_t)d[3] * a.src_pitch;
 #pragma unroll
                         for (int q = 0; q < kDenseRegs; ++q) {
                             const uint32_t w = (uint32_t)(q * kWave + lane);
-                            if (w < gw_reg) dacc[q] |= r0[w] | r1[w] | r2[w] | r3[w];
+                            if (w < gw_reg) {
+                                uint64_t x = 0;
+#pragma unroll
+                                for (int i = 0; i < kDenseRows; ++i) x |= rr[i][w];
+                                dacc[q] |= x;
+                            }
                         }
-                        for (uint32_t w = gw_reg + lane; w < a.gw; w += kWave) acc[w] |= r0[w] | r1[w] | r2[w] | r3[w];
+                        for (uint32_t w = gw_reg + lane; w < a.gw; w += kWave) {
+                            uint64_t x = 0;
+#pragma unroll
+                            for (int i = 0; i < kDenseRows; ++i) x |= rr[i][w];
+                            acc[w] |= x;
+                        }
                     }
                     any = true;
                     __builtin_amdgcn_wave_barrier();
