@@ -249,6 +249,34 @@ cfpq_status cfpq_result_stats(cfpq_result res, uint32_t *iterations, uint64_t *d
 cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_t v,
                               uint32_t *edges, uint64_t cap_edges, uint64_t *n_edges);
 
+/* ------------------------------------------------------------------------
+ * All paths of bounded length (Sec. 3.2, paths extraction; Listing 2).  The
+ * set of paths between two vertices can be infinite; this enumerates the
+ * paths from u to v with at most max_edges edges whose words box derives,
+ * each path once, in order of non-decreasing length, one length at a time
+ * as cfpq_paths_next asks for them.  The empty path is included when
+ * u == v and box derives the empty word.
+ *
+ * cfpq_paths_open: requires a result kept with keep_rank (n <= 16384); the
+ * iterator copies what it needs, so res may be destroyed afterwards.  If
+ * (u, v) is not in box's relation (as returned, vertex masks included) the
+ * iterator is empty.  Errors: CFPQ_ERR_INVALID (NULL arguments, box or
+ * vertex out of range, no ranks kept).
+ * cfpq_paths_next: the next path into edges (3 uint32 per edge: src, label,
+ * dst).  CFPQ_ERR_NOT_FOUND when no path is left; CFPQ_ERR_BUFFER with
+ * *n_edges set if cap_edges is too small (the path is kept for the next
+ * call); CFPQ_ERR_LIMIT if the paths of one length exceed 2^24 edges.
+ * Host computation: the RSM is taken as a grammar (a nonterminal per state
+ * for the words leading from it to a final state), made free of epsilon and
+ * unit rules, and expanded with every split pruned by memoised sets of
+ * vertices reachable from (nonterminal, vertex) in exactly l edges.
+ * ---------------------------------------------------------------------- */
+typedef struct cfpq_paths_s *cfpq_paths;
+cfpq_status cfpq_paths_open(cfpq_result res, uint32_t box, uint32_t u, uint32_t v, uint32_t max_edges,
+                            cfpq_paths *out);
+cfpq_status cfpq_paths_next(cfpq_paths it, uint32_t *edges, uint64_t cap_edges, uint64_t *n_edges);
+void cfpq_paths_close(cfpq_paths it);
+
 /* Per-kernel profile of a query run with opts.profile (levels strategy).
  * kind: CFPQ_KERNEL_SEED (Kronecker product with the new edges),
  * CFPQ_KERNEL_LEVEL (one frontier level of the incremental closure) or

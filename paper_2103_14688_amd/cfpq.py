@@ -29,7 +29,8 @@ EXPORTS = [
     "cfpq_graph_create", "cfpq_graph_info", "cfpq_graph_destroy", "cfpq_rsm_create", "cfpq_rsm_destroy",
     "cfpq_query", "cfpq_query_batch", "cfpq_result_count", "cfpq_result_hash", "cfpq_result_bitmap",
     "cfpq_result_pairs", "cfpq_result_block", "cfpq_result_stats", "cfpq_result_profile", "cfpq_extract_path",
-    "cfpq_result_destroy", "cfpq_last_error", "cfpq_version",
+    "cfpq_result_destroy", "cfpq_last_error", "cfpq_version", "cfpq_paths_open", "cfpq_paths_next",
+    "cfpq_paths_close",
 ]
 
 
@@ -83,12 +84,14 @@ def load():
         "cfpq_result_stats": [vp, P(u32), vp, u32, P(ctypes.c_double)],
         "cfpq_result_profile": [vp, u32, P(u64), P(ctypes.c_double), P(u64)],
         "cfpq_extract_path": [vp, u32, u32, u32, vp, u64, P(u64)],
+        "cfpq_paths_open": [vp, u32, u32, u32, u32, P(vp)],
+        "cfpq_paths_next": [vp, vp, u64, P(u64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
-    for name in ("cfpq_graph_destroy", "cfpq_rsm_destroy", "cfpq_result_destroy"):
+    for name in ("cfpq_graph_destroy", "cfpq_rsm_destroy", "cfpq_result_destroy", "cfpq_paths_close"):
         getattr(lib, name).argtypes = [vp]
         getattr(lib, name).restype = None
     lib.cfpq_last_error.restype = ctypes.c_char_p
@@ -326,6 +329,32 @@ def cfpq_extract_path(res, box, u, v):
     return out
 
 
+def cfpq_paths_open(res, box, u, v, max_edges):
+    out = ctypes.c_void_p()
+    _check(load().cfpq_paths_open(res, box, u, v, max_edges, ctypes.byref(out)))
+    return out.value
+
+
+def cfpq_paths_next(it, cap=64):
+    """The next path as an (edges, 3) array, or None when none is left."""
+    lib = load()
+    n = ctypes.c_uint64()
+    while True:
+        buf = np.zeros((cap, 3), dtype=np.uint32)
+        st = lib.cfpq_paths_next(it, _ptr(buf), cap, ctypes.byref(n))
+        if st == OK:
+            return buf[:n.value].copy()
+        if st == ERR_NOT_FOUND:
+            return None
+        if st != ERR_BUFFER:
+            _check(st)
+        cap = int(n.value)
+
+
+def cfpq_paths_close(it):
+    load().cfpq_paths_close(it)
+
+
 def cfpq_result_destroy(res):
     load().cfpq_result_destroy(res)
 
@@ -419,6 +448,19 @@ class Result:
 
     def extract_path(self, u, v, box=0):
         return cfpq_extract_path(self.h, self.box(box), u, v)
+
+    def paths(self, u, v, max_edges, box=0):
+        """All paths u -> v with at most max_edges edges whose words the box
+        derives, each once, shortest first (a generator over (k, 3) arrays)."""
+        it = cfpq_paths_open(self.h, self.box(box), u, v, max_edges)
+        try:
+            while True:
+                p = cfpq_paths_next(it)
+                if p is None:
+                    return
+                yield p
+        finally:
+            cfpq_paths_close(it)
 
     def close(self):
         if self.h:

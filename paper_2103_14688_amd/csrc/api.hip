@@ -12,6 +12,9 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <unordered_set>
+#include <unordered_map>
+#include <functional>
 
 #include "../../include/cfpq.h"
 #include "internal.h"
@@ -1626,6 +1629,231 @@ extern "C" cfpq_status cfpq_extract_path(cfpq_result r, uint32_t box, uint32_t u
 }
 
 extern "C" void cfpq_result_destroy(cfpq_result r) { delete r; }
+
+// ---------------------------------------------------------------------------
+// all paths of bounded length (Sec. 3.2, paths extraction)
+//
+// Grammar view of the RSM: X_q derives the words that lead from state q to a
+// final state of q's box (rules X_q -> eps if q is final, X_q -> T_t X_q' for
+// a terminal transition, X_q -> X_start(N) X_q' for a box-labelled one; T_t
+// -> t), so box N's language is L(X_start(N)).  Removing epsilon rules gives
+// A+ (the non-empty words of A) with rules A+ -> B+ C+, A+ -> C+ (B nullable)
+// and A+ -> B+ (C nullable); unit rules are closed once (U(A)).  Every
+// binary split then gives both parts at least one edge, so the expansion of
+// a length-l path recurses on shorter lengths only and always terminates.
+// F(A, x, l) = vertices y with a length-l path x -> y derived from A+,
+// memoised as bitsets, prunes every split.
+// ---------------------------------------------------------------------------
+struct cfpq_paths_s {
+    uint32_t n = 0, W = 0, nQ = 0, nT = 0;
+    std::vector<uint32_t> out_off, out;                             // successors per label (sorted)
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> bin;    // A+ -> B+ C+
+    std::vector<std::vector<uint32_t>> unit;                        // U(A), A included
+    std::vector<uint8_t> nullable;
+    uint32_t S = 0, u = 0, v = 0, max_edges = 0, next_len = 0;
+    std::unordered_map<uint64_t, std::vector<uint64_t>> memo;
+    std::vector<std::vector<uint32_t>> batch;                       // paths of the current length
+    size_t pos = 0;
+    bool empty = false;
+
+    uint64_t key(uint32_t A, uint32_t x, uint32_t l) const {
+        return ((uint64_t)A * n + x) * (uint64_t)(max_edges + 1) + l;
+    }
+    bool has_edge(uint32_t x, uint32_t t, uint32_t y) const {
+        const uint32_t *b = out.data() + out_off[(uint64_t)t * (n + 1) + x];
+        const uint32_t *e = out.data() + out_off[(uint64_t)t * (n + 1) + x + 1];
+        return std::binary_search(b, e, y);
+    }
+    static bool test(const std::vector<uint64_t> &s, uint32_t y) { return (s[y >> 6] >> (y & 63)) & 1ull; }
+
+    const std::vector<uint64_t> &F(uint32_t A, uint32_t x, uint32_t l) {
+        const uint64_t k = key(A, x, l);
+        auto it = memo.find(k);
+        if (it != memo.end()) return it->second;
+        std::vector<uint64_t> s(W, 0);
+        for (uint32_t B : unit[A]) {
+            if (B >= nQ) {   // T_t
+                if (l == 1) {
+                    const uint32_t t = B - nQ;
+                    for (uint32_t e = out_off[(uint64_t)t * (n + 1) + x]; e < out_off[(uint64_t)t * (n + 1) + x + 1]; ++e)
+                        s[out[e] >> 6] |= 1ull << (out[e] & 63);
+                }
+                continue;
+            }
+            for (const auto &cd : bin[B])
+                for (uint32_t l1 = 1; l1 < l; ++l1) {
+                    const std::vector<uint64_t> fc = F(cd.first, x, l1);   // copy: the memo grows below
+                    for (uint32_t w = 0; w < W; ++w)
+                        for (uint64_t m = fc[w]; m; m &= m - 1) {
+                            const uint32_t z = w * 64 + (uint32_t)__builtin_ctzll(m);
+                            const std::vector<uint64_t> &fd = F(cd.second, z, l - l1);
+                            for (uint32_t i = 0; i < W; ++i) s[i] |= fd[i];
+                        }
+                }
+        }
+        return memo.emplace(k, std::move(s)).first->second;
+    }
+
+    // every derivation of a length-l path x -> y from A+; k runs with path
+    // holding the path so far
+    void gen(uint32_t A, uint32_t x, uint32_t y, uint32_t l, std::vector<uint32_t> &path,
+             const std::function<void()> &k) {
+        for (uint32_t B : unit[A]) {
+            if (B >= nQ) {
+                const uint32_t t = B - nQ;
+                if (l == 1 && has_edge(x, t, y)) {
+                    path.insert(path.end(), {x, t, y});
+                    k();
+                    path.resize(path.size() - 3);
+                }
+                continue;
+            }
+            for (const auto &cd : bin[B])
+                for (uint32_t l1 = 1; l1 < l; ++l1) {
+                    const std::vector<uint64_t> fc = F(cd.first, x, l1);
+                    for (uint32_t w = 0; w < W; ++w)
+                        for (uint64_t m = fc[w]; m; m &= m - 1) {
+                            const uint32_t z = w * 64 + (uint32_t)__builtin_ctzll(m);
+                            if (!test(F(cd.second, z, l - l1), y)) continue;
+                            gen(cd.first, x, z, l1, path, [&] { gen(cd.second, z, y, l - l1, path, k); });
+                        }
+                }
+        }
+    }
+
+    struct VecHash {
+        size_t operator()(const std::vector<uint32_t> &p) const {
+            uint64_t h = 1469598103934665603ull;
+            for (uint32_t x : p) h = (h ^ x) * 1099511628211ull;
+            return (size_t)h;
+        }
+    };
+
+    cfpq_status fill(uint32_t l) {
+        batch.clear();
+        pos = 0;
+        if (l == 0) {
+            if (u == v && nullable[S]) batch.emplace_back();
+            return CFPQ_OK;
+        }
+        if (!test(F(S, u, l), v)) return CFPQ_OK;
+        std::unordered_set<std::vector<uint32_t>, VecHash> seen;
+        std::vector<uint32_t> path;
+        uint64_t words = 0;
+        bool over = false;
+        gen(S, u, v, l, path, [&] {
+            if (over) return;
+            if (seen.insert(path).second) {
+                words += path.size();
+                if (words > (1ull << 24) * 3) over = true;
+                else batch.push_back(path);
+            }
+        });
+        if (over) return fail(CFPQ_ERR_LIMIT, "paths of one length exceed 2^24 edges");
+        return CFPQ_OK;
+    }
+};
+
+extern "C" cfpq_status cfpq_paths_open(cfpq_result r, uint32_t box, uint32_t u, uint32_t v, uint32_t max_edges,
+                                       cfpq_paths *out) {
+    if (!out) return fail(CFPQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    cfpq_status st = check_box(r, box);
+    if (st != CFPQ_OK) return st;
+    if (!r->rank.p) return fail(CFPQ_ERR_INVALID, "ranks were not kept (keep_rank)");
+    if (u >= r->n || v >= r->n) return fail(CFPQ_ERR_INVALID, "vertex out of range");
+    if (max_edges > 4096) return fail(CFPQ_ERR_INVALID, "max_edges above 4096");
+    try {
+        std::unique_ptr<cfpq_paths_s> it(new cfpq_paths_s);
+        const cfpq_rsm_s &R = r->rsm;
+        it->n = r->n;
+        it->W = (r->n + 63) / 64;
+        it->nQ = R.n_states;
+        it->nT = R.n_terms;
+        it->u = u;
+        it->v = v;
+        it->max_edges = max_edges;
+        it->out_off = r->out_off;
+        it->out = r->out;
+        for (uint64_t i = 0; i + 1 < it->out_off.size(); ++i)
+            std::sort(it->out.begin() + it->out_off[i], it->out.begin() + it->out_off[i + 1]);
+        const uint32_t nA = it->nQ + it->nT;
+        // nullable X_q: least fixpoint
+        it->nullable.assign(nA, 0);
+        for (uint32_t q = 0; q < it->nQ; ++q) it->nullable[q] = R.is_final[q] != 0;
+        auto sym_nt = [&](uint32_t sym) { return sym < R.n_terms ? it->nQ + sym : R.box_start[sym - R.n_terms]; };
+        for (bool grew = true; grew;) {
+            grew = false;
+            for (size_t t = 0; t < R.t_src.size(); ++t) {
+                const uint32_t q = R.t_src[t];
+                if (!it->nullable[q] && it->nullable[sym_nt(R.t_sym[t])] && it->nullable[R.t_dst[t]]) {
+                    it->nullable[q] = 1;
+                    grew = true;
+                }
+            }
+        }
+        // epsilon-free rules
+        it->bin.assign(nA, {});
+        std::vector<std::vector<uint32_t>> unit_edges(nA);
+        for (size_t t = 0; t < R.t_src.size(); ++t) {
+            const uint32_t A = R.t_src[t], B = sym_nt(R.t_sym[t]), C = R.t_dst[t];
+            it->bin[A].push_back({B, C});
+            if (it->nullable[B]) unit_edges[A].push_back(C);
+            if (it->nullable[C]) unit_edges[A].push_back(B);
+        }
+        it->unit.assign(nA, {});
+        for (uint32_t A = 0; A < nA; ++A) {
+            std::vector<uint8_t> in(nA, 0);
+            std::vector<uint32_t> q{A};
+            in[A] = 1;
+            for (size_t h = 0; h < q.size(); ++h)
+                for (uint32_t B : unit_edges[q[h]])
+                    if (!in[B]) {
+                        in[B] = 1;
+                        q.push_back(B);
+                    }
+            it->unit[A] = q;
+        }
+        it->S = R.box_start[box];
+        // the pair must be in the relation as returned (masks included)
+        uint64_t word = 0;
+        HIP_TRY(hipMemcpy(&word, r->NT.as<uint64_t>() + ((uint64_t)box * r->n + v) * r->P + (u >> 6), 8,
+                          hipMemcpyDeviceToHost));
+        it->empty = !((word >> (u & 63)) & 1ull);
+        *out = it.release();
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    return CFPQ_OK;
+}
+
+extern "C" cfpq_status cfpq_paths_next(cfpq_paths it, uint32_t *edges, uint64_t cap_edges, uint64_t *n_edges) {
+    if (!it || !n_edges) return fail(CFPQ_ERR_INVALID, "NULL argument");
+    try {
+        while (!it->empty && it->pos >= it->batch.size()) {
+            if (it->next_len > it->max_edges) {
+                it->empty = true;
+                break;
+            }
+            cfpq_status st = it->fill(it->next_len++);
+            if (st != CFPQ_OK) return st;
+        }
+        if (it->empty) return fail(CFPQ_ERR_NOT_FOUND, "no path left");
+        const std::vector<uint32_t> &p = it->batch[it->pos];
+        *n_edges = p.size() / 3;
+        if (cap_edges < p.size() / 3) return fail(CFPQ_ERR_BUFFER, "edge buffer too small");
+        if (!p.empty()) {
+            if (!edges) return fail(CFPQ_ERR_INVALID, "edges is NULL");
+            std::memcpy(edges, p.data(), p.size() * 4);
+        }
+        ++it->pos;
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
+    return CFPQ_OK;
+}
+
+extern "C" void cfpq_paths_close(cfpq_paths it) { delete it; }
 
 extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
 
