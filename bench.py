@@ -52,7 +52,7 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=8, help="execution slots (streams) of the batched server")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--workload", choices=["rpq", "brackets", "samegen", "alias"], default="rpq",
+    ap.add_argument("--workload", choices=["rpq", "brackets", "samegen", "alias", "paths"], default="rpq",
                     help="rpq (default, the headline) or one of the other measured workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 3 times (reference kernel for the "
@@ -228,6 +228,8 @@ def other_workload(args):
                     "config": {"workload": "S -> a S b | a b on directed Erdos-Renyi n=256, p=2/n per label",
                                **res}})
         return out
+    if args.workload == "paths":
+        return paths_workload(args, out)
     if args.workload == "samegen":
         g, depth = synth.hierarchy(args.n, seed=synth.BASE_SEED + 3)
         text = synth.SAME_GEN_G1
@@ -265,6 +267,44 @@ def other_workload(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_gather<false> (closure frontier level)"},
+    })
+    return out
+
+
+def paths_workload(args, out):
+    """All paths of at most 20 edges (the bound of the paper's experiment,
+    Sec. 4.2) for same-generation G1 on a hierarchy graph, over sampled pairs
+    of the relation: time and number of paths per pair."""
+    import numpy as np
+
+    import synth
+    from paper_2103_14688_amd import cfpq, rsm
+
+    n = min(args.n, 4000)
+    g, _ = synth.hierarchy(n, seed=synth.BASE_SEED + 3)
+    R = rsm.from_grammar(synth.SAME_GEN_G1, g.labels)
+    res = cfpq.query(cfpq.Graph.from_synth(g), cfpq.Query(R), keep_rank=True)
+    pairs = res.pairs(0)
+    rng = np.random.default_rng(synth.BASE_SEED + 11)
+    pick = pairs[rng.choice(len(pairs), size=min(200, len(pairs)), replace=False)]
+    times, counts, edges = [], [], 0
+    for u, v in pick.tolist():
+        t0 = time.perf_counter()
+        k = 0
+        for p in res.paths(int(u), int(v), 20):
+            k += 1
+            edges += len(p)
+        times.append(time.perf_counter() - t0)
+        counts.append(k)
+    total = sum(times)
+    out.update({
+        "metric": "paths extracted per second (all paths of at most 20 edges per pair)",
+        "value": sum(counts) / total if total else 0.0, "unit": "paths/s", "ms_per_step": 1e3 * total / len(pick),
+        "config": {"workload": f"same-generation G1 on hierarchy n={n}, all paths of <= 20 edges for "
+                               f"{len(pick)} sampled pairs of the relation", "n": n, "pairs_in_relation": len(pairs),
+                   "ms_per_pair_mean": 1e3 * total / len(pick), "ms_per_pair_max": 1e3 * max(times),
+                   "paths_per_pair_mean": float(np.mean(counts)), "paths_per_pair_max": int(max(counts)),
+                   "edges_returned": edges},
     })
     return out
 
