@@ -591,6 +591,17 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, res.src_mask.as<uint64_t>(), s));
     HIP_TRY(launch_eps(d_NT, d_dNT, dnt_act.as<uint64_t>(), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
                        Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+    // the seed's selectors (new nonterminal edges) are scanned once per source
+    // tile: with long rows, a summary of their non-zero words, rebuilt after
+    // every write-back, lets the scan skip the empty blocks
+    DevBuf dsum;
+    const uint32_t sum_pitch = (Pn + kWave - 1) / kWave;
+    const bool use_sum = sparse_nt && Pn >= kSelSumMinWords;
+    if (use_sum) {
+        if (!dsum.alloc(al, (uint64_t)nB * n * sum_pitch * 8, s))
+            return fail(CFPQ_ERR_OOM, "device allocation failed (selector summary)");
+        HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dnt_act.as<uint64_t>(), dsum.as<uint64_t>(), sum_pitch, s));
+    }
 
     std::vector<uint64_t> box_delta(nB, 0);
     for (uint32_t b : p.eps_boxes) box_delta[b] = n;
@@ -643,10 +654,12 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             // and the first chunk of levels always fit before a ring clear
             if ((st = need_slots(levels_hint + 2)) != CFPQ_OK) return st;
             a.sel = d_dNT; a.sel_act = dnt_act.as<uint64_t>();
+            a.sel_sum = use_sum ? dsum.as<uint64_t>() : nullptr; a.sum_pitch = sum_pitch;
             a.src = d_T; a.src_pitch = P; a.src_off = w0; a.src_act = tnz.as<uint64_t>();
             a.dn = Dbuf[0]; a.actn = act[0]; a.act_clear = nullptr;
             a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1);
             a.extra = nullptr; a.extra_act = nullptr;
+            if ((st = prof_mark(0)) != CFPQ_OK) return st;   // the seed's time includes its sparse product
             if (sparse_nt) {
                 // the product rows go to the other frontier buffer and the third
                 // activity bitset, both unused until the first level
@@ -657,7 +670,6 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 a.extra = Dbuf[1]; a.extra_act = act[2];
             }
             const uint32_t seed_slot = slot;
-            if ((st = prof_mark(0)) != CFPQ_OK) return st;
             HIP_TRY(launch_gather(a, true, grid, s));
             if ((st = prof_mark(1)) != CFPQ_OK) return st;
             if (prof) {
@@ -692,7 +704,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                         return fail(CFPQ_ERR_OOM, "device allocation failed (matrix-core product)");
                 }
                 for (uint32_t j = 0; j < k; ++j, ++li) {
-                    a.sel = d_NT; a.sel_act = nullptr;
+                    a.sel = d_NT; a.sel_act = nullptr; a.sel_sum = nullptr;
                     a.src = Dbuf[(li - 1) & 1]; a.src_pitch = G; a.src_off = 0;
                     a.src_act = act[(li - 1) % 3];
                     a.dn = Dbuf[li & 1]; a.actn = act[li % 3]; a.act_clear = act[(li + 1) % 3];
@@ -777,6 +789,8 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         w.iter = it; w.ctr = d_ctr; w.slot_base = slot;
         if ((st = prof_mark(0)) != CFPQ_OK) return st;
         HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
+        if (use_sum)
+            HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dnt_act.as<uint64_t>(), dsum.as<uint64_t>(), sum_pitch, s));
         if ((st = prof_mark(1)) != CFPQ_OK) return st;
         if ((st = fetch(slot, nB)) != CFPQ_OK) return st;
         if (prof) {

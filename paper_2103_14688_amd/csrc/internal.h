@@ -65,7 +65,17 @@ struct GatherArgs {
     uint32_t seed_terms;          // seed launch: terminal transitions take part
     const uint64_t *extra;        // seed: rows of the sparse nonterminal product [nQ][n][G] (or null:
     const uint64_t *extra_act;    //   nonterminal transitions OR whole rows), row bitset [nQ][Pn]
+    const uint64_t *sel_sum;      // optional summary of the selector rows: bit w of row word w / 64
+                                  // set iff selector word w may be non-zero, [rows][sum_pitch]
+    uint32_t sum_pitch;
 };
+// selector summaries pay from this many words per row on
+constexpr uint32_t kSelSumMinWords = 1024;
+// summary of the rows [nB][n][P] whose bit is set in act ([nB][Pn] bits;
+// other rows' summaries are left as they are): bit w % 64 of summary word
+// w / 64 set iff word w is non-zero
+hipError_t launch_row_summary(const uint64_t *rows, uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn,
+                              const uint64_t *act, uint64_t *sum, uint32_t sum_pitch, hipStream_t s);
 
 constexpr uint32_t kEll = 16;                  // listed bits per source row in the sparse product
 constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole

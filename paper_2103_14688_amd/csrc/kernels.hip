@@ -117,6 +117,31 @@ __global__ void k_mask_rows(uint64_t *rows, uint32_t n, uint32_t P, uint32_t Pn,
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_row_summary(const uint64_t *rows, uint32_t nB, uint32_t n, uint32_t P,
+                                                        uint32_t Pn, const uint64_t *act, uint64_t *sum,
+                                                        uint32_t sum_pitch) {
+    const int lane = __lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t r = wave; r < (uint64_t)nB * n; r += nwaves) {
+        const uint32_t N = (uint32_t)(r / n), v = (uint32_t)(r % n);
+        if (!test_bit(act + (uint64_t)N * Pn, v)) continue;
+        const uint64_t *row = rows + r * P;
+        for (uint32_t k0 = 0; k0 < Pn; k0 += kWave) {
+            const uint32_t k = k0 + (uint32_t)lane;
+            const uint64_t m = __ballot(k < Pn && row[k] != 0);
+            if (lane == 0) sum[r * sum_pitch + k0 / kWave] = m;
+        }
+    }
+}
+
+hipError_t launch_row_summary(const uint64_t *rows, uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn,
+                              const uint64_t *act, uint64_t *sum, uint32_t sum_pitch, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_summary, dim3(grid_for((uint64_t)nB * n * kWave)), dim3(kBlock), 0, s, rows, nB, n, P, Pn,
+                       act, sum, sum_pitch);
+    return hipGetLastError();
+}
+
 hipError_t launch_mask_rows(uint64_t *rows, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *src,
                             const uint64_t *dst, hipStream_t s) {
     hipLaunchKernelGGL(k_mask_rows, dim3(grid_for((uint64_t)n * Pn)), dim3(kBlock), 0, s, rows, n, P, Pn, src, dst);
@@ -223,7 +248,12 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                 for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
                     const uint32_t k = k0 + lane;
                     uint64_t wb = 0;
-                    if (k < a.Pn) wb = sel[k] & sact[k];
+                    if (k < a.Pn) {
+                        // the activity word first: the selector is read only
+                        // where some source row is live
+                        const uint64_t sa = sact[k];
+                        if (sa) wb = sel[k] & sa;
+                    }
                     uint64_t m = __ballot(wb != 0);
                     fed |= (m != 0);
                     while (m) {
@@ -360,10 +390,19 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             if (a.sel_act && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
             const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
             const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
+            const uint64_t *ssum = a.sel_sum ? a.sel_sum + ((uint64_t)N * a.n + v) * a.sum_pitch : nullptr;
             for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
                 const uint32_t k = k0 + lane;
+                // with a summary, only words that may be non-zero are read
+                const uint64_t live = ssum ? ssum[k0 / kWave] : ~0ull;
+                if (!live) continue;
                 uint64_t wb = 0;
-                if (k < a.Pn) wb = sel[k] & sact[k];
+                if (k < a.Pn && ((live >> lane) & 1ull)) {
+                    // the activity word first: the selector is read only
+                    // where some source row is live
+                    const uint64_t sa = sact[k];
+                    if (sa) wb = sel[k] & sa;
+                }
                 uint64_t m = __ballot(wb != 0);
                 if (m && !cleared) {
                     for (uint32_t w = lane; w < a.gw; w += kWave) acc[w] = 0;

@@ -414,3 +414,29 @@ def test_sparse_product_runs_in_closure_levels():
     _, _, rows = run(g, R, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS, profile=True)
     assert rows.profile(cfpq.KERNEL_NT_SPARSE)[0] == 0
     assert rows.stats()[:2] == res.stats()[:2]
+
+
+def test_large_same_generation_selector_summary():
+    # rows of at least 1024 words: the seed reads its selectors (the new
+    # nonterminal edges) through a summary of their non-zero words; checked
+    # against the closed form (pairs of vertices at equal depth >= 1, count
+    # and order-independent hash) untiled and tiled, and against whole-row OR
+    g, depth = synth.hierarchy(70000, with_type=False, seed=81)
+    R = rsm_mod.from_grammar(synth.SAME_GEN_SC, g.labels)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS)
+    levels = np.bincount(depth)
+    assert res.count(0) == int((levels[1:] ** 2).sum())
+    want = np.uint64(0)
+    with np.errstate(over="ignore"):
+        for d in range(1, len(levels)):
+            vs = np.nonzero(depth == d)[0].astype(np.uint64)
+            for c in range(0, len(vs), 512):
+                keys = (vs[c:c + 512, None] << np.uint64(32)) | vs[None, :]
+                want += H.splitmix64_np(keys.ravel()).sum(dtype=np.uint64)
+    assert res.hash(0) == int(want)
+    tiled = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=300)
+    assert (tiled.count(0), tiled.hash(0)) == (res.count(0), res.hash(0))
+    rows = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS)
+    assert rows.stats()[:2] == res.stats()[:2] and rows.hash(0) == res.hash(0)
