@@ -824,6 +824,90 @@ __device__ void block_fill(uint64_t *p, uint64_t words) {
     for (uint64_t i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
 }
 
+// Rows of at most kNarrowWords words (n <= 512): one thread per row instead
+// of one wavefront, which would leave all but a few lanes idle; the fused
+// kernel walks its rows this way.
+constexpr uint32_t kNarrowWords = 8;
+
+template <bool SEED>
+__device__ bool gather_row_thread(const GatherArgs &a, uint32_t f, uint32_t v, unsigned long long &cnt) {
+    const uint32_t tb = a.in_off[f], te = a.in_off[f + 1];
+    if (tb == te) return false;
+    uint64_t acc[kNarrowWords];
+#pragma unroll
+    for (uint32_t w = 0; w < kNarrowWords; ++w) acc[w] = 0;
+    bool fed = false;
+    auto take = [&](const uint64_t *r) {
+#pragma unroll
+        for (uint32_t w = 0; w < kNarrowWords; ++w)
+            if (w < a.gw) acc[w] |= r[w];
+        fed = true;
+    };
+    for (uint32_t t = tb; t < te; ++t) {
+        const InTrans tr = a.in_tr[t];
+        const uint64_t *rows = a.src + (uint64_t)tr.src * a.n * a.src_pitch + a.src_off;
+        const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
+        if (tr.sym < a.n_terms) {
+            if (SEED && !a.seed_terms) continue;
+            const uint32_t *op = a.goff + (uint64_t)tr.sym * (a.n + 1) + v;
+            for (uint32_t e = op[0]; e < op[1]; ++e) {
+                const uint32_t x = a.gidx[e];
+                if (test_bit(sact, x)) take(rows + (uint64_t)x * a.src_pitch);
+            }
+        } else {
+            const uint32_t N = tr.sym - a.n_terms;
+            if (SEED && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
+            const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
+            for (uint32_t k = 0; k < a.Pn; ++k)
+                for (uint64_t b = sel[k] & sact[k]; b; b &= b - 1)
+                    take(rows + (uint64_t)(k * 64 + (uint32_t)__builtin_ctzll(b)) * a.src_pitch);
+        }
+    }
+    if (!fed) return false;
+    uint64_t *trow = a.T + ((uint64_t)f * a.n + v) * a.P + a.w0;
+    uint64_t *drow = a.dn + ((uint64_t)f * a.n + v) * a.G;
+    bool any = false;
+#pragma unroll
+    for (uint32_t w = 0; w < kNarrowWords; ++w) {
+        if (w < a.gw) {
+            const uint64_t t = trow[w];
+            const uint64_t nw = acc[w] & ~t;
+            if (nw) {
+                trow[w] = t | nw;
+                any = true;
+                cnt += (unsigned long long)__popcll(nw);
+            }
+            drow[w] = nw;
+        }
+    }
+    return any;
+}
+
+// write-back of one row (N, v) by one thread (narrow rows; see writeback_row)
+__device__ bool writeback_row_thread(const WritebackArgs &a, uint32_t N, uint32_t v, unsigned long long &cnt_box) {
+    const uint32_t fb = a.fin_off[N], fe = a.fin_off[N + 1];
+    uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
+    uint64_t *dnt = a.dNT + ((uint64_t)N * a.n + v) * a.P;
+    bool any = false;
+    for (uint32_t k = 0; k < a.Pn; ++k) {
+        uint64_t acc = 0;
+        for (uint32_t i = fb; i < fe; ++i) acc |= a.T[((uint64_t)a.fin[i] * a.n + v) * a.P + k];
+        const uint64_t old = nt[k];
+        const uint64_t nw = acc & ~old;
+        if (nw) {
+            nt[k] = old | nw;
+            any = true;
+            cnt_box += (unsigned long long)__popcll(nw);
+            if (a.rank)
+                for (uint64_t bits = nw; bits; bits &= bits - 1)
+                    a.rank[((uint64_t)N * a.n + v) * a.n + (uint64_t)k * 64 + __builtin_ctzll(bits)] =
+                        (uint8_t)(a.iter > 255 ? 255 : a.iter);
+        }
+        dnt[k] = nw;
+    }
+    return any;
+}
+
 __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
                           unsigned long long *s_box) {
     const int lane = __lane_id();
@@ -879,6 +963,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     wb.state_flags = nullptr; wb.multi = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
+    const bool narrow = Q.Pn <= kNarrowWords;
     uint32_t it = 0;
     unsigned long long status = 0;
     for (;;) {
@@ -899,12 +984,22 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
         if (threadIdx.x == 0) *s_cnt = 0;
         __syncthreads();
         unsigned long long cnt = 0;
-        for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
-            const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
-            bool fed;
-            if (gather_row<true>(a, f, v, cnt, fed) && lane == 0) {
-                atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
-                atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+        if (narrow) {
+            for (uint64_t r = threadIdx.x; r < (uint64_t)Q.nQ * Q.n; r += blockDim.x) {
+                const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                if (gather_row_thread<true>(a, f, v, cnt)) {
+                    atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                }
+            }
+        } else {
+            for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
+                const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                bool fed;
+                if (gather_row<true>(a, f, v, cnt, fed) && lane == 0) {
+                    atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                }
             }
         }
         cnt = wave_sum(cnt);
@@ -921,12 +1016,22 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
             a.sel = Q.NT; a.sel_act = nullptr; a.src = D; a.src_pitch = Q.P; a.src_off = 0;
             a.src_act = act; a.dn = Dn; a.actn = actn;
             cnt = 0;
-            for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
-                const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
-                bool fed;
-                if (gather_row<false>(a, f, v, cnt, fed) && lane == 0) {
-                    atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
-                    atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+            if (narrow) {
+                for (uint64_t r = threadIdx.x; r < (uint64_t)Q.nQ * Q.n; r += blockDim.x) {
+                    const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                    if (gather_row_thread<false>(a, f, v, cnt)) {
+                        atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                        atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    }
+                }
+            } else {
+                for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
+                    const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                    bool fed;
+                    if (gather_row<false>(a, f, v, cnt, fed) && lane == 0) {
+                        atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                        atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    }
                 }
             }
             cnt = wave_sum(cnt);
@@ -938,16 +1043,28 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
         if (threadIdx.x < Q.nB) s_box[threadIdx.x] = 0;
         __syncthreads();
         wb.iter = it;
-        for (uint64_t r = wave; r < (uint64_t)Q.nB * Q.n; r += nwaves) {
-            const uint32_t N = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
-            if (Q.fin_off[N] == Q.fin_off[N + 1]) continue;
-            unsigned long long c = 0;
-            bool any = false;
-            writeback_row(wb, N, v, c, any);
-            c = wave_sum(c);
-            if (lane == 0 && any) {
-                atomicOr((unsigned long long *)&Q.dnt_act[(uint64_t)N * Q.Pn + (v >> 6)], 1ull << (v & 63));
-                atomicAdd(&s_box[N], c);
+        if (narrow) {
+            for (uint64_t r = threadIdx.x; r < (uint64_t)Q.nB * Q.n; r += blockDim.x) {
+                const uint32_t N = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                if (Q.fin_off[N] == Q.fin_off[N + 1]) continue;
+                unsigned long long c = 0;
+                if (writeback_row_thread(wb, N, v, c)) {
+                    atomicOr((unsigned long long *)&Q.dnt_act[(uint64_t)N * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    atomicAdd(&s_box[N], c);
+                }
+            }
+        } else {
+            for (uint64_t r = wave; r < (uint64_t)Q.nB * Q.n; r += nwaves) {
+                const uint32_t N = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
+                if (Q.fin_off[N] == Q.fin_off[N + 1]) continue;
+                unsigned long long c = 0;
+                bool any = false;
+                writeback_row(wb, N, v, c, any);
+                c = wave_sum(c);
+                if (lane == 0 && any) {
+                    atomicOr((unsigned long long *)&Q.dnt_act[(uint64_t)N * Q.Pn + (v >> 6)], 1ull << (v & 63));
+                    atomicAdd(&s_box[N], c);
+                }
             }
         }
         __syncthreads();
