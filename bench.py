@@ -46,6 +46,8 @@ def main():
     ap.add_argument("--nt-mode", choices=["auto", "rows", "mfma"], default="auto",
                     help="box-labelled transitions in closure levels (grammar workloads): automatic, "
                          "whole-row OR, or the int8 matrix-core product")
+    ap.add_argument("--recompute", action="store_true",
+                    help="grammar workloads: recompute the closure from scratch every iteration")
     ap.add_argument("--cpu-sources", type=int, default=20000, help="oracle sample size (sources)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400)
@@ -241,7 +243,8 @@ def other_workload(args):
     q = cfpq.Query(R)
     nt_mode = {"auto": cfpq.NT_AUTO, "rows": cfpq.NT_ROWS, "mfma": cfpq.NT_MFMA}[args.nt_mode]
     rs, dt = timed(lambda: cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, tile_words=args.tile_words,
-                                      profile=True, nt_mode=nt_mode), args.steps, args.warmup)
+                                      profile=True, nt_mode=nt_mode, recompute=args.recompute),
+                   args.steps, args.warmup)
     r = rs[-1]
     it, deltas, ms = r.stats()
     pairs = r.count(0)
@@ -262,6 +265,7 @@ def other_workload(args):
                    "level": {"launches": lv[0], "ms": lv[1], "GB": lv[2] / 1e9},
                    "seed": {"launches": sd[0], "ms": sd[1]}, "writeback": {"launches": wb[0], "ms": wb[1]},
                    "nt_mode": args.nt_mode, "nt_sparse": {"launches": sp[0], "ms": sp[1]},
+                   "closure": "recomputed each iteration" if args.recompute else "incremental",
                    "nt_mfma": {"launches": mf[0], "ms": mf[1], "int8_TOPS": mf[2] / (mf[1] * 1e9) if mf[1] else 0.0,
                                "frac_of_int8_peak": mf[2] / (mf[1] * 1e9) / INT8_PEAK_TOPS if mf[1] else 0.0}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

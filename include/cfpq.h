@@ -156,6 +156,11 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                picks the matrix cores: with sparse frontiers the dense
  *                product moves and multiplies far more than the bit-serial OR.
  *                The answer does not depend on the mode.
+ *   recompute  : nonzero: every iteration of the levels strategy recomputes
+ *                the closure from scratch over the whole M2 (the variant the
+ *                paper evaluated, Sec. 6) instead of extending it from the
+ *                new edges A2 only (Sec. 3.1.1).  Same answers, iterations
+ *                and per-iteration counts; for comparison.
  *   profile    : record HIP events around every launch of the levels
  *                strategy (see cfpq_result_profile); adds ~1 us per launch.
  *   stream     : hipStream_t for all work of the call (NULL = null stream).
@@ -186,7 +191,7 @@ typedef struct {
     uint32_t tile_words;
     uint32_t profile;
     uint32_t nt_mode;
-    uint32_t reserved;
+    uint32_t recompute;
     void *stream;
     const cfpq_allocator *alloc;
     const uint64_t *src_mask;

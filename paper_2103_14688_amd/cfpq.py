@@ -51,7 +51,7 @@ class Allocator(ctypes.Structure):
 class QueryOpts(ctypes.Structure):
     _fields_ = [("strategy", ctypes.c_uint32), ("max_iters", ctypes.c_uint32), ("keep_rank", ctypes.c_uint32),
                 ("keep_blocks", ctypes.c_uint32), ("tile_words", ctypes.c_uint32), ("profile", ctypes.c_uint32),
-                ("nt_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("nt_mode", ctypes.c_uint32), ("recompute", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("alloc", ctypes.POINTER(Allocator)),
                 ("src_mask", ctypes.c_void_p), ("dst_mask", ctypes.c_void_p)]
 
@@ -227,11 +227,12 @@ def vertex_mask(mask, n):
 
 
 def make_opts(strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-              stream=None, alloc=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None):
+              stream=None, alloc=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None,
+              recompute=False):
     """Options struct; masks must be word arrays (vertex_mask) that the caller
     keeps alive until the call returns."""
-    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(nt_mode), 0,
-                  stream, None, None, None)
+    o = QueryOpts(strategy, max_iters, int(keep_rank), int(keep_blocks), tile_words, int(profile), int(nt_mode),
+                  int(recompute), stream, None, None, None)
     if alloc is not None:
         o.alloc = ctypes.pointer(alloc)
     if src_mask is not None:
@@ -475,14 +476,14 @@ class Result:
 
 
 def query(graph, q, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False, tile_words=0,
-          stream=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None):
+          stream=None, profile=False, nt_mode=NT_AUTO, src_mask=None, dst_mask=None, recompute=False):
     """src_mask / dst_mask: bool arrays of length n or ceil(n/64) uint64
     words restricting the start box's sources / targets (None = all)."""
     if stream is None:
         stream = current_stream()
     sm, dm = vertex_mask(src_mask, graph.n), vertex_mask(dst_mask, graph.n)
     o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, nt_mode,
-                  sm, dm)
+                  sm, dm, recompute)
     return Result(cfpq_query(graph.h, q.h, o), graph, q)
 
 

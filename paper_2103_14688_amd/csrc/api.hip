@@ -605,6 +605,14 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
 
     std::vector<uint64_t> box_delta(nB, 0);
     for (uint32_t b : p.eps_boxes) box_delta[b] = n;
+    // from-scratch closure per iteration (the evaluated variant): the seed
+    // takes every edge of M2, all rows selectable
+    const bool scratch = o.recompute != 0;
+    DevBuf ones;
+    if (scratch) {
+        if (!ones.alloc(al, (uint64_t)nB * Pn * 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed");
+        HIP_TRY(launch_fill(ones.as<uint64_t>(), (uint64_t)nB * Pn, ~0ull, s));
+    }
 
     PinnedCounters pc;
     if (!pc.ensure(4096 * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
@@ -641,6 +649,12 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             res.deltas.push_back(0);
             break;
         }
+        if (scratch && it > 1) {   // forget the closure: only the box-start rows' own bits
+            HIP_TRY(launch_fill(d_T, qw, 0, s));
+            HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
+            HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, res.src_mask.as<uint64_t>(),
+                                     s));
+        }
         for (uint32_t gi = 0; gi < groups; ++gi) {
             const uint32_t w0 = gi * G, gw = std::min(G, Pn - w0);
             HIP_TRY(launch_fill(act[0], 3 * aw, 0, s));
@@ -653,11 +667,11 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             // Kronecker product of the RSM with the new edges (seed); the seed
             // and the first chunk of levels always fit before a ring clear
             if ((st = need_slots(levels_hint + 2)) != CFPQ_OK) return st;
-            a.sel = d_dNT; a.sel_act = dnt_act.as<uint64_t>();
-            a.sel_sum = use_sum ? dsum.as<uint64_t>() : nullptr; a.sum_pitch = sum_pitch;
+            a.sel = scratch ? d_NT : d_dNT; a.sel_act = scratch ? ones.as<uint64_t>() : dnt_act.as<uint64_t>();
+            a.sel_sum = use_sum && !scratch ? dsum.as<uint64_t>() : nullptr; a.sum_pitch = sum_pitch;
             a.src = d_T; a.src_pitch = P; a.src_off = w0; a.src_act = tnz.as<uint64_t>();
             a.dn = Dbuf[0]; a.actn = act[0]; a.act_clear = nullptr;
-            a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1);
+            a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1) || scratch;
             a.extra = nullptr; a.extra_act = nullptr;
             if ((st = prof_mark(0)) != CFPQ_OK) return st;   // the seed's time includes its sparse product
             if (sparse_nt) {

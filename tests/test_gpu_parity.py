@@ -440,3 +440,35 @@ def test_large_same_generation_selector_summary():
     assert (tiled.count(0), tiled.hash(0)) == (res.count(0), res.hash(0))
     rows = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, nt_mode=cfpq.NT_ROWS)
     assert rows.stats()[:2] == res.stats()[:2] and rows.hash(0) == res.hash(0)
+
+
+# closure recomputed from scratch each iteration (the variant the paper
+# evaluated) against the incremental closure: same relation, iterations and
+# per-iteration counts; one case also against the oracle
+@pytest.mark.parametrize("case", ["samegen", "alias", "brackets", "nullable", "tiled"])
+def test_recompute_matches_incremental(case):
+    text = synth.BRACKETS
+    kw = {}
+    if case == "samegen":
+        g, _ = synth.hierarchy(2500, seed=91)
+        text = synth.SAME_GEN_G1
+    elif case == "alias":
+        g = synth.clustered(1500, cluster=(16, 64), seed=92)
+        text = synth.MEM_ALIAS
+    elif case == "nullable":
+        g = synth.erdos_renyi(300, seed=93)
+        text = "S -> a S b S | eps"
+    else:
+        g = synth.erdos_renyi(900, seed=94)
+        kw = {"tile_words": 5} if case == "tiled" else {}
+    R = rsm_mod.from_grammar(text, g.labels)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    inc = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, **kw)
+    scr = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, recompute=True, **kw)
+    assert scr.stats()[:2] == inc.stats()[:2]
+    for b in range(R.n_boxes):
+        assert (scr.count(b), scr.hash(b)) == (inc.count(b), inc.hash(b))
+    if case in ("alias", "nullable"):
+        want = H.oracle_grammar(g, text)[R.box_names[0]][1]
+        check_box(scr, want, g.n)
