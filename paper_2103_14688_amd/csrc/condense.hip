@@ -346,6 +346,13 @@ __device__ __forceinline__ uint64_t *comp_row(uint32_t c, uint32_t n, uint32_t P
 constexpr uint32_t kCondPredCap = 8;     // predecessor rows listed per node; more take the whole-wave path
 // lanes per node when OR-ing rows (kWave / kCondGroupLanes nodes at a time);
 // a compile-time tuning parameter
+// nodes per step of the row phase with a whole wavefront per node (their
+// row loads in flight together); 0 selects the lane-group path instead.
+// Compile-time tuning parameters: 2 measured fastest (3 and 4 cost
+// occupancy), ahead of lane groups of 16 or 32 lanes per node
+#ifndef CFPQ_COND_PAIR
+#define CFPQ_COND_PAIR 2
+#endif
 #ifndef CFPQ_COND_GROUP_LANES
 #define CFPQ_COND_GROUP_LANES 64
 #endif
@@ -590,8 +597,105 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
         __builtin_amdgcn_wave_barrier();
         const uint32_t my_cnt = s_cnt[wib][lane];
         const uint64_t over = __ballot(at && my_cnt > kCondPredCap);
-        // B. four nodes at a time
+        // B. the listed nodes' rows
         uint64_t pend = todo & ~over;
+#if CFPQ_COND_PAIR
+        // whole wavefront per node, kNS nodes per step: the row loads of all
+        // of them are issued before any is waited for
+        static_assert(kCondGroupLanes == kWave, "groups of whole-wavefront nodes");
+        constexpr int kNS = CFPQ_COND_PAIR;
+        while (pend) {
+            int jn[kNS];
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) {
+                jn[q] = pend ? __ffsll((unsigned long long)pend) - 1 : -1;
+                if (jn[q] >= 0) pend &= pend - 1;
+            }
+            uint32_t cN[kNS], vN[kNS], fqN[kNS], cntN[kNS], sgN[kNS];
+            uint64_t ownN[kNS];
+            bool doN[kNS], aliasN[kNS], seedN[kNS], anyN[kNS];
+            uint32_t kmax = 0;
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) {
+                const int j = jn[q] < 0 ? jn[0] : jn[q];
+                cN[q] = (uint32_t)__builtin_amdgcn_readlane((int)cm, j);
+                vN[q] = (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+                fqN[q] = (uint32_t)__builtin_amdgcn_readlane((int)fq, j);
+                cntN[q] = jn[q] < 0 ? 0u : (uint32_t)__builtin_amdgcn_readlane((int)my_cnt, j);
+                sgN[q] = (uint32_t)__builtin_amdgcn_readlane((int)single, j);
+                ownN[q] = shfl_u64(own, j);
+                const bool seeded = sgN[q] && (fqN[q] & kStartState) && (!g.src_mask || mask_bit(g.src_mask, vN[q]));
+                const uint32_t sw = vN[q] >> 6;
+                seedN[q] = jn[q] >= 0 && seeded && sw >= pass0 && sw < pass0 + cw;
+                anyN[q] = cntN[q] > 0 || seedN[q];
+                aliasN[q] = jn[q] >= 0 && sgN[q] && (fqN[q] & kAliasFinal);
+                doN[q] = jn[q] >= 0 && (anyN[q] || aliasN[q]);
+                kmax = cntN[q] > kmax ? cntN[q] : kmax;
+            }
+            uint64_t acc[kNS][kCondPassWords];
+#pragma unroll
+            for (int q = 0; q < kNS; ++q)
+#pragma unroll
+                for (int kk = 0; kk < kCondPassWords; ++kk) acc[q][kk] = 0;
+            for (uint32_t k = 0; k < kmax; ++k) {
+                const uint64_t *src[kNS];
+                uint64_t keep[kNS];
+#pragma unroll
+                for (int q = 0; q < kNS; ++q) {
+                    // past a node's list: re-read the first node's row (k is
+                    // inside the longest list, found first), masked off
+                    const bool in = k < cntN[q];
+                    int jj = jn[0];
+#pragma unroll
+                    for (int r = 0; r < kNS; ++r)
+                        if (k < cntN[r]) { jj = jn[r]; break; }
+                    if (in) jj = jn[q];
+                    src[q] = off_ptr(s_pred[wib][jj][k], R, NT) + pass0;
+                    keep[q] = in ? ~0ull : 0ull;
+                }
+                uint64_t x[kNS][kCondPassWords];
+#pragma unroll
+                for (int q = 0; q < kNS; ++q)
+#pragma unroll
+                    for (int kk = 0; kk < kCondPassWords; ++kk) {
+                        const uint32_t w = (uint32_t)(kk * kWave + lane);
+                        x[q][kk] = w < cw ? src[q][w] : 0ull;
+                    }
+#pragma unroll
+                for (int q = 0; q < kNS; ++q)
+#pragma unroll
+                    for (int kk = 0; kk < kCondPassWords; ++kk) acc[q][kk] |= x[q][kk] & keep[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kNS; ++q) {
+                if (!doN[q]) continue;
+                uint64_t *row = off_ptr(ownN[q], R, NT) + pass0;
+                unsigned long long pc = 0;
+#pragma unroll
+                for (int kk = 0; kk < kCondPassWords; ++kk) {
+                    const uint32_t w = (uint32_t)(kk * kWave + lane);
+                    if (seedN[q] && w == (vN[q] >> 6) - pass0) acc[q][kk] |= 1ull << (vN[q] & 63);
+                    if (w < cw) {
+                        if (sgN[q])
+                            row[w] = acc[q][kk];
+                        else if (acc[q][kk])
+                            atomicOr((unsigned long long *)&row[w], acc[q][kk]);
+                        if (aliasN[q]) pc += (unsigned long long)__popcll(acc[q][kk]);
+                    }
+                }
+                if (aliasN[q]) {
+                    const uint32_t box = fqN[q] >> kFlagBoxShift;
+                    if (box == 0) pairs0 += pc;
+                    else if (pc) atomicAdd(&box_pairs[box * kWave], pc);
+                }
+                if (lane == 0) {
+                    if (anyN[q]) nz[(uint64_t)cN[q] * nch + ch] = 1;
+                    words_w += cw;
+                    words_r += (unsigned long long)cntN[q] * cw;
+                }
+            }
+        }
+#else
         while (pend) {
             int jg = -1;
 #pragma unroll
@@ -660,6 +764,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
                 words_r += (unsigned long long)cntj * cw;
             }
         }
+#endif
         for (uint64_t ov = over; ov;) {
             const int j = __ffsll((unsigned long long)ov) - 1;
             ov &= ov - 1;
