@@ -48,6 +48,30 @@ __device__ __forceinline__ void for_preds(const ProdGraph &g, uint32_t p, F &&fn
     }
 }
 
+// Does some predecessor (successor) x of p pass test(x)?  Four edges per
+// step: their index, flag and mark loads are independent, so they are in
+// flight together instead of one edge's chain after another's.
+template <bool SUCC, class F>
+__device__ __forceinline__ bool any_adj(const ProdGraph &g, uint32_t p, F &&test) {
+    const uint32_t q = p / g.n, v = p - q * g.n;
+    const uint32_t tb = SUCC ? g.out_off[q] : g.in_off[q], te = SUCC ? g.out_off[q + 1] : g.in_off[q + 1];
+    for (uint32_t t = tb; t < te; ++t) {
+        const InTrans tr = SUCC ? g.out_tr[t] : g.in_tr[t];
+        const uint32_t *o = (SUCC ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
+        const uint32_t *idx = SUCC ? g.sidx : g.gidx;
+        const uint32_t b = o[0], e = o[1], base = tr.src * g.n;
+        uint32_t i = b;
+        for (; i + 4 <= e; i += 4) {
+            const uint32_t x0 = base + idx[i], x1 = base + idx[i + 1], x2 = base + idx[i + 2], x3 = base + idx[i + 3];
+            const bool h0 = test(x0), h1 = test(x1), h2 = test(x2), h3 = test(x3);
+            if (h0 | h1 | h2 | h3) return true;
+        }
+        for (; i < e; ++i)
+            if (test(base + idx[i])) return true;
+    }
+    return false;
+}
+
 template <class F>
 __device__ __forceinline__ void for_succs(const ProdGraph &g, uint32_t p, F &&fn) {
     const uint32_t q = p / g.n, v = p - q * g.n;
@@ -78,16 +102,9 @@ __global__ void k_trim(ProdGraph g, uint8_t *alive, uint32_t *scc, const unsigne
     unsigned long long c = 0;
     NODE_LOOP(N) {
         if (!alive[p]) continue;
-        bool in = false, out = false;
-        for_preds(g, p, [&](uint32_t x) {
-            if (x != p && alive[x]) { in = true; return false; }
-            return true;
-        });
-        if (in)
-            for_succs(g, p, [&](uint32_t x) {
-                if (x != p && alive[x]) { out = true; return false; }
-                return true;
-            });
+        auto live_other = [&](uint32_t x) { return x != p && alive[x] != 0; };
+        const bool in = any_adj<false>(g, p, live_other);
+        const bool out = in && any_adj<true>(g, p, live_other);
         if (!in || !out) {
             alive[p] = 0;
             scc[p] = p;
@@ -102,9 +119,17 @@ __global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *b
     unsigned long long mine = 0;
     NODE_LOOP(N) {
         if (!alive[p]) continue;
+        // degrees from the offsets: no edge is read
         uint64_t din = 0, dout = 0;
-        for_preds(g, p, [&](uint32_t) { ++din; return true; });
-        for_succs(g, p, [&](uint32_t) { ++dout; return true; });
+        const uint32_t q = p / g.n, v = p - q * g.n;
+        for (uint32_t t = g.in_off[q]; t < g.in_off[q + 1]; ++t) {
+            const uint32_t *o = g.goff + (uint64_t)g.in_tr[t].sym * (g.n + 1) + v;
+            din += o[1] - o[0];
+        }
+        for (uint32_t t = g.out_off[q]; t < g.out_off[q + 1]; ++t) {
+            const uint32_t *o = g.soff + (uint64_t)g.out_tr[t].sym * (g.n + 1) + v;
+            dout += o[1] - o[0];
+        }
         uint64_t score = (din + 1) * (dout + 1);
         if (score > 0xFFFFFFFFull) score = 0xFFFFFFFFull;
         const unsigned long long key = (score << 32) | p;
@@ -128,27 +153,13 @@ __global__ void k_reach(ProdGraph g, const uint8_t *alive, uint32_t *fw, uint32_
     unsigned long long c = 0;
     NODE_LOOP(N) {
         if (!alive[p]) continue;
-        if (!fw[p]) {
-            bool hit = false;
-            for_preds(g, p, [&](uint32_t x) {
-                if (alive[x] && fw[x]) { hit = true; return false; }
-                return true;
-            });
-            if (hit) {
-                fw[p] = 1;
-                ++c;
-            }
+        if (!fw[p] && any_adj<false>(g, p, [&](uint32_t x) { return alive[x] && fw[x]; })) {
+            fw[p] = 1;
+            ++c;
         }
-        if (!bw[p]) {
-            bool hit = false;
-            for_succs(g, p, [&](uint32_t x) {
-                if (alive[x] && bw[x]) { hit = true; return false; }
-                return true;
-            });
-            if (hit) {
-                bw[p] = 1;
-                ++c;
-            }
+        if (!bw[p] && any_adj<true>(g, p, [&](uint32_t x) { return alive[x] && bw[x]; })) {
+            bw[p] = 1;
+            ++c;
         }
     }
     count_add(ctr, c);
@@ -229,12 +240,7 @@ __global__ void k_color_back(ProdGraph g, const uint8_t *alive, const uint32_t *
     NODE_LOOP(N) {
         if (!alive[p] || found[p]) continue;
         const uint32_t cp = color[p];
-        bool hit = false;
-        for_succs(g, p, [&](uint32_t x) {
-            if (alive[x] && found[x] && color[x] == cp) { hit = true; return false; }
-            return true;
-        });
-        if (hit) {
+        if (any_adj<true>(g, p, [&](uint32_t x) { return alive[x] && found[x] && color[x] == cp; })) {
             found[p] = 1;
             scc[p] = cp;
             ++c;
