@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=400)
     ap.add_argument("--serve-nmax", type=int, default=20000)
     ap.add_argument("--serve-slots", type=int, default=8, help="execution slots (streams) of the batched server")
+    ap.add_argument("--serve-rates", default="0.5,1,2,4",
+                    help="open-loop arrival rates as multiples of the plain closed-loop throughput")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--workload", choices=["rpq", "brackets", "samegen", "alias", "paths"], default="rpq",
                     help="rpq (default, the headline) or one of the other measured workloads")
@@ -330,10 +332,13 @@ def measure_serving(args):
                                             n_range=(1000, args.serve_nmax))
     graphs = [synth.serving_graph(n, seed, labels) for n, seed in recipes]
     handles = [cfpq.Graph.from_synth(g) for g in graphs]
+    print(f"# serving: {len(graphs)} graphs resident", file=sys.stderr, flush=True)
     comp = []
     for gi, kind, text in qs:
         R = rsm.from_regex(text, labels) if kind == "regex" else rsm.from_grammar(text, labels)
         comp.append((gi, R, cfpq.Query(R)))
+        if len(comp) % 1000 == 0:
+            print(f"# serving: {len(comp)} queries compiled", file=sys.stderr, flush=True)
 
     def requests():
         return [serve.Request(i, handles[gi], q, graphs[gi].n, R.n_states, R.n_boxes)
@@ -348,9 +353,21 @@ def measure_serving(args):
         if arrivals is None:
             for r in rs:
                 srv.submit(r)
-            srv.drain()
+            # report every 1000 finished requests (long mixes run for minutes)
+            shown = 0
+            while True:
+                try:
+                    srv.drain(timeout=1.0)
+                    break
+                except TimeoutError:
+                    done = len(srv.finished) // 1000
+                    if done > shown:
+                        shown = done
+                        print(f"# serving {mode}: {done * 1000} finished", file=sys.stderr, flush=True)
         else:
-            serve.replay(srv, rs, arrivals)
+            serve.replay(srv, rs, arrivals,
+                         report=lambda k: print(f"# serving {mode} open loop: {k} submitted", file=sys.stderr,
+                                                flush=True))
         wall = time.perf_counter() - t0
         srv.close()
         bad = [r.error for r in rs if r.error]
@@ -359,14 +376,17 @@ def measure_serving(args):
 
     print(f"# serving: {len(comp)} queries on 64 graphs, n <= {args.serve_nmax}", file=sys.stderr, flush=True)
     run("batched")                                   # warm-up (allocator, code objects)
+    print("# serving: warm-up done", file=sys.stderr, flush=True)
     plain, wall_p, _ = run("plain")
+    print(f"# serving: plain closed loop {wall_p:.1f} s", file=sys.stderr, flush=True)
     batched, wall_b, srv_b = run("batched")
+    print(f"# serving: batched closed loop {wall_b:.1f} s", file=sys.stderr, flush=True)
     same = all(a.result == b.result for a, b in zip(plain, batched))
     pairs = sum(r.result[0] for r in plain)
     mu = len(plain) / wall_p
     same_open = True
     sweep = []
-    for factor in (0.5, 1.0, 2.0, 4.0):
+    for factor in [float(x) for x in args.serve_rates.split(",") if x]:
         lam = factor * mu
         arr = np.cumsum(np.random.default_rng(synth.BASE_SEED + 9).exponential(1.0 / lam, size=len(comp)))
         plain_o, _, _ = run("plain", arr)

@@ -179,15 +179,18 @@ class Server:
             w.join()
 
 
-def replay(server, requests, arrivals):
-    """Submit requests at the given arrival offsets (seconds) and wait for all."""
+def replay(server, requests, arrivals, report=None, every=1000):
+    """Submit requests at the given arrival offsets (seconds) and wait for all;
+    report(k), if given, runs after every `every` submissions."""
     t0 = server.now()
-    for r, a in zip(requests, arrivals):
+    for i, (r, a) in enumerate(zip(requests, arrivals)):
         delay = t0 + a - server.now()
         if delay > 0:
             time.sleep(delay)
         r.arrival = t0 + a
         server.submit(r)
+        if report and (i + 1) % every == 0:
+            report(i + 1)
     server.drain()
     return requests
 
