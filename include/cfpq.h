@@ -144,7 +144,11 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *   keep_rank  : keep, for every nonterminal pair, the iteration that added
  *                it; required by cfpq_extract_path (n <= 16384).
  *   keep_blocks: keep the closure blocks, required by cfpq_result_block.
- *   tile_words : source-tile width in 64-bit words (0 = automatic).
+ *   tile_words : source-tile width in 64-bit words (levels strategy; the
+ *                closure runs once per tile of sources).  0 = automatic:
+ *                the widest tile whose frontier buffers fit in the free
+ *                device memory left after the closure state, at most 4096
+ *                words when the sparse nonterminal product applies.
  *   nt_mode    : how box-labelled transitions are multiplied (levels
  *                strategy): CFPQ_NT_AUTO = sparse rows (ELL lists + LDS
  *                accumulators) in the Kronecker seed, and in closure levels

@@ -499,10 +499,30 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     if (st != CFPQ_OK) return st;
 
     const uint32_t n = p.n, P = p.P, Pn = p.Pn, nQ = p.nQ, nB = p.nB;
-    uint32_t G = o.tile_words ? std::min<uint32_t>(o.tile_words, Pn) : Pn;
+    const uint64_t qw = (uint64_t)nQ * n * P, bw = (uint64_t)nB * n * P;
+    // source tile: given, or the widest that fits -- at most kSparseMaxWords
+    // words when the sparse nonterminal product applies (it keeps a tile row
+    // in LDS), and within the device memory left once the closure (T), the
+    // nonterminal matrices and the indexes are placed; the frontier buffers
+    // (two, plus the product rows) take 3 nQ n words per word of tile
+    uint32_t G = Pn;
+    if (o.tile_words) {
+        G = std::min<uint32_t>(o.tile_words, Pn);
+    } else {
+        if (!p.nt_src.empty() && o.nt_mode != CFPQ_NT_ROWS) G = std::min<uint32_t>(G, kSparseMaxWords);
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            const double fixed = 8.0 * ((double)qw + 2.0 * (double)bw) + 4.0 * nQ * (double)n * (kEll + 1) +
+                                 8.0 * nB * (double)n * ((Pn + 63) / 64) + (o.keep_rank ? (double)nB * n * n : 0.0) +
+                                 (256.0 * (1 << 20));
+            const double per_word = 8.0 * 3.0 * nQ * (double)n;
+            const double room = 0.92 * (double)free_b - fixed;
+            if (room < per_word * G) G = room >= per_word ? (uint32_t)(room / per_word) : 1u;
+        }
+    }
     if (G == 0) G = 1;
     const uint32_t groups = (Pn + G - 1) / G;
-    const uint64_t qw = (uint64_t)nQ * n * P, bw = (uint64_t)nB * n * P, fw = (uint64_t)nQ * n * G;
+    const uint64_t fw = (uint64_t)nQ * n * G;
     const uint64_t aw = (uint64_t)nQ * Pn;
     const uint64_t ring_words = (uint64_t)kRingSlots * kSlotWords;
 
