@@ -147,8 +147,10 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *   tile_words : source-tile width in 64-bit words (levels strategy; the
  *                closure runs once per tile of sources).  0 = automatic:
  *                the widest tile whose frontier buffers fit in the free
- *                device memory left after the closure state, at most 4096
- *                words when the sparse nonterminal product applies.
+ *                device memory left after the closure state, at most 1200
+ *                words when box-labelled transitions use the sparse product
+ *                (narrower tiles keep more frontier rows sparse), split
+ *                into equal tiles.
  *   nt_mode    : how box-labelled transitions are multiplied (levels
  *                strategy): CFPQ_NT_AUTO = sparse rows (ELL lists + LDS
  *                accumulators) in the Kronecker seed, and in closure levels

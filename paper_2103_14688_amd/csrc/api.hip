@@ -509,7 +509,10 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     if (o.tile_words) {
         G = std::min<uint32_t>(o.tile_words, Pn);
     } else {
-        if (!p.nt_src.empty() && o.nt_mode != CFPQ_NT_ROWS) G = std::min<uint32_t>(G, kSparseMaxWords);
+        // with box-labelled transitions, narrower tiles also keep more
+        // frontier rows within an ELL list (fewer whole-row ORs): measured
+        // best near 800-1600 words, so tiles of at most kTileCapWords, equal
+        if (!p.nt_src.empty() && o.nt_mode != CFPQ_NT_ROWS) G = std::min<uint32_t>(G, kTileCapWords);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
             const double fixed = 8.0 * ((double)qw + 2.0 * (double)bw) + 4.0 * nQ * (double)n * (kEll + 1) +
@@ -519,6 +522,9 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             const double room = 0.92 * (double)free_b - fixed;
             if (room < per_word * G) G = room >= per_word ? (uint32_t)(room / per_word) : 1u;
         }
+        if (G == 0) G = 1;
+        const uint32_t tiles = (Pn + G - 1) / G;
+        G = (Pn + tiles - 1) / tiles;   // equal tiles rather than a ragged last one
     }
     if (G == 0) G = 1;
     const uint32_t groups = (Pn + G - 1) / G;

@@ -82,6 +82,9 @@ constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole
 // closure levels use the sparse product from this many words per row tile
 // (narrower rows are ORed whole at no greater cost)
 constexpr uint32_t kLevelSparseMinWords = 16;
+// automatic source tiles of queries with box-labelled transitions: at most
+// this many words (see run_levels)
+constexpr uint32_t kTileCapWords = 1200;
 constexpr uint32_t kSparseMaxWords = 4096;     // LDS row accumulator limit (words per wavefront)
 
 struct WritebackArgs {

@@ -371,7 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
     // registers, kDenseRegs words per lane (the first kDenseRegs * 64 words
     // of the tile; the rest through LDS), kDenseRows rows per step so that
     // their loads are in flight together
-    constexpr int kDenseRegs = 8;
+#ifndef CFPQ_DENSE_REGS
+#define CFPQ_DENSE_REGS 8
+#endif
+    constexpr int kDenseRegs = CFPQ_DENSE_REGS;
 #ifndef CFPQ_DENSE_ROWS
 #define CFPQ_DENSE_ROWS 2
 #endif
