@@ -77,7 +77,10 @@ constexpr uint32_t kSelSumMinWords = 1024;
 hipError_t launch_row_summary(const uint64_t *rows, uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn,
                               const uint64_t *act, uint64_t *sum, uint32_t sum_pitch, hipStream_t s);
 
-constexpr uint32_t kEll = 16;                  // listed bits per source row in the sparse product
+#ifndef CFPQ_ELL
+#define CFPQ_ELL 32
+#endif
+constexpr uint32_t kEll = CFPQ_ELL;            // listed bits per source row in the sparse product (tuning)
 constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole
 // closure levels use the sparse product from this many words per row tile
 // (narrower rows are ORed whole at no greater cost)
