@@ -330,14 +330,6 @@ __global__ void k_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *st
     count_add(ctr, c);
 }
 
-// one topological level: every node whose component sits at level L ORs the
-// rows of its predecessors' components (outside its own) into its
-// component's row, then releases its successors' components.  Work items are
-// (block of 64 consecutive nodes, 512-word chunk of the row): a wavefront
-// selects the block's nodes at level L by ballot and handles them one at a
-// time over its chunk; predecessors are filtered lane-parallel (component id,
-// external, not a repeat of the last row OR-ed); the chunk-0 wavefront also
-// releases the successors' components with lane-parallel atomics.
 // Row of component c: single-member components of a state flagged
 // kAliasFinal (the only final state of its box) keep their row in the answer
 // matrix M2^N itself (row v of box N), all other components in R.
@@ -521,9 +513,11 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 //   A. edge-parallel over the items' in-edges: predecessor components with a
 //      non-empty chunk go to a short LDS list per node (with their row
 //      offsets, so the OR loop issues nothing but row loads);
-//   B. four nodes at a time, 16 lanes each, OR their listed rows (32 words
-//      per lane in flight) and write the chunk; nodes with longer lists take
-//      the whole-wavefront path;
+//   B. the whole wavefront ORs a listed node's rows (8 words per lane), two
+//      nodes per step with all their row loads in flight together, and
+//      writes the chunk (CFPQ_COND_PAIR = 0 selects lane groups of
+//      CFPQ_COND_GROUP_LANES lanes per node instead); nodes with longer
+//      lists take the whole-wavefront path;
 //   C. (first chunk only) edge-parallel over the out-edges: retire the
 //      in-degree stripes of successor components and release them into
 //      level L + 1.

@@ -298,12 +298,12 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
 }
 
 // ---------------------------------------------------------------------------
-// sparse nonterminal product for the Kronecker seed: when the closure rows of
-// the source state hold few bits (e.g. the rows after one inverse edge),
-// OR-ing whole rows per selector bit wastes a row of loads per bit.  The rows
-// are listed instead (ELL: up to kEll set-bit positions per row, denser rows
-// flagged), and each target row gathers the listed bits of its selected
-// predecessors into an LDS row accumulator.
+// sparse nonterminal product (Kronecker seed and closure levels): when the
+// source rows hold few bits in the tile (closure rows after one inverse
+// edge, frontier rows), OR-ing whole rows per selector bit wastes a row of
+// loads per bit.  The rows are listed instead (ELL: up to kEll set-bit
+// positions per row, denser rows flagged), and each target row gathers the
+// listed bits of its selected predecessors into an LDS row accumulator.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x) {
     const int lane = __lane_id();
@@ -354,9 +354,10 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
 }
 
 // one wavefront per target row (f, v): OR over every nonterminal transition
-// (s, N, f) and every new edge (x, v) of N (dNT row v) of the source row
-// (s, x), gathered bit by bit from the ELL list (or whole, if dense) into an
-// LDS accumulator of gw words; the result goes to extra[(f, v)]
+// (s, N, f) and every selected edge (x, v) of N (seed: the new edges, dNT
+// row v; levels: all of M2^N) of the live source row (s, x): listed rows bit
+// by bit into an LDS accumulator of gw words, dense rows whole into
+// registers; the result goes to extra[(f, v)]
 __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32_t *ell_cnt,
                                                        const uint32_t *ell_idx, uint64_t *extra,
                                                        uint64_t *extra_act) {
