@@ -1009,10 +1009,20 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         // the pivot key lives past the launch counters, which a long chain
         // clears and reuses
         unsigned long long *best = cc + 2 * kCtr;
+        // frontiers: four node arrays that are free until the colouring
+        // (color) and the condensation (pending, qa, qb); their size ring
+        // after the pivot key
+        ReachQueues rq{};
+        rq.q[0][0] = qa;
+        rq.q[0][1] = qb;
+        rq.q[1][0] = color;
+        rq.q[1][1] = pending;
+        rq.cnt = cc + 2 * kCtr + 1;
+        rq.cap = N;
         HIP_TRY(launch_pivot(pg, alive, best, s));
-        HIP_TRY(launch_pivot_seed(best, fw, bwm, s));
-        st = chain([&](uint32_t, const unsigned long long *pv, unsigned long long *c) {
-            return launch_reach(pg, alive, fw, bwm, pv, c, s);
+        HIP_TRY(launch_pivot_seed(best, fw, bwm, rq, s));
+        st = chain([&](uint32_t i, const unsigned long long *, unsigned long long *c) {
+            return launch_reach(pg, alive, fw, bwm, rq, i, c, s);
         }, chunk0(g.hint_reach, 8), &g.hint_reach);
         if (st != CFPQ_OK) return st;
         if ((st = next_slot(1)) != CFPQ_OK) return st;

@@ -92,6 +92,26 @@ __device__ __forceinline__ void count_add(unsigned long long *ctr, unsigned long
     if (__lane_id() == 0 && c) atomicAdd(ctr, c);
 }
 
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src, kWave); }
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
+    return (uint64_t)shfl_u32((uint32_t)x, src) | ((uint64_t)shfl_u32((uint32_t)(x >> 32), src) << 32);
+}
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const int lane = __lane_id();
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, off, kWave);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t y = (uint32_t)__shfl_xor((int)x, off, kWave);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
 // ----------------------------------------------------------------------------
 // component search
 // ----------------------------------------------------------------------------
@@ -142,37 +162,112 @@ __global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *b
     if (__lane_id() == 0 && mine) atomicMax(best, mine);
 }
 
-// one sweep of forward and backward reachability from the pivot, restricted
-// to live nodes, marking in place: a live node with a marked live predecessor
-// joins fw, one with a marked live successor joins bw.  Sweeps repeat until
-// one marks nothing.
-__global__ void k_reach(ProdGraph g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
-                        const unsigned long long *prev, unsigned long long *ctr) {
-    if (prev && *prev == 0) return;  // the previous sweep marked nothing
-    const uint32_t N = g.nQ * g.n;
-    unsigned long long c = 0;
-    NODE_LOOP(N) {
-        if (!alive[p]) continue;
-        if (!fw[p] && any_adj<false>(g, p, [&](uint32_t x) { return alive[x] && fw[x]; })) {
-            fw[p] = 1;
-            ++c;
+// Forward and backward reachability from the pivot inside the live nodes,
+// level by level: launch it expands frontier it of both directions (forward
+// along successors, backward along predecessors), 64 edges per step per
+// wavefront whatever the frontier nodes' degrees.  A live, unmarked neighbour
+// is claimed with an atomic exchange of its mark and appended to frontier
+// it + 1.  A node is claimed at most once per direction, so a frontier never
+// holds more than N entries.  Frontier sizes live in a ring of three counters
+// per direction: launch it reads slot it % 3, appends to slot (it + 1) % 3 and
+// clears slot (it + 2) % 3, which launch it - 1 read and launch it + 1 fills.
+__global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
+                                                  ReachQueues rq, uint32_t it, unsigned long long *ctr) {
+    __shared__ uint32_t s_scan[kBlock / kWave][kWave];
+    const uint32_t r0 = it % 3, r1 = (it + 1) % 3, r2 = (it + 2) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rq.cnt[r2] = 0;
+        rq.cnt[3 + r2] = 0;
+    }
+    const uint64_t nf = rq.cnt[r0], nb = rq.cnt[3 + r0];
+    if (nf + nb == 0) return;  // both searches are complete
+    const int lane = __lane_id();
+    const uint32_t wib = threadIdx.x / kWave;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const uint64_t itf = (nf + kWave - 1) / kWave, items = itf + (nb + kWave - 1) / kWave;
+    const uint64_t below = (1ull << lane) - 1ull;
+    unsigned long long claimed = 0;
+    for (uint64_t w = wave; w < items; w += nwaves) {
+        const bool fwd = w < itf;   // wave-uniform
+        const uint64_t base = (fwd ? w : w - itf) * kWave;
+        const uint64_t cnt = fwd ? nf : nb;
+        const uint32_t d = fwd ? 0u : 1u;
+        const uint32_t *cur = rq.q[d][it & 1];
+        uint32_t *nxt = rq.q[d][(it + 1) & 1];
+        uint32_t *mark = fwd ? fw : bw;
+        unsigned long long *tail = rq.cnt + 3 * d + r1;
+        const uint32_t *idx = fwd ? g.sidx : g.gidx;
+        uint32_t v = 0, tb = 0, te = 0;
+        if (base + lane < cnt) {
+            const uint32_t y = cur[base + lane];
+            const uint32_t q = y / g.n;
+            v = y - q * g.n;
+            tb = fwd ? g.out_off[q] : g.in_off[q];
+            te = fwd ? g.out_off[q + 1] : g.in_off[q + 1];
         }
-        if (!bw[p] && any_adj<true>(g, p, [&](uint32_t x) { return alive[x] && bw[x]; })) {
-            bw[p] = 1;
-            ++c;
+        const uint32_t ntr = wave_max_u32(te - tb);
+        for (uint32_t k = 0; k < ntr; ++k) {
+            uint32_t b = 0, e = 0, sb = 0;
+            if (tb + k < te) {
+                // in_tr: (source state, label); out_tr: (target state, label)
+                const InTrans tr = fwd ? g.out_tr[tb + k] : g.in_tr[tb + k];
+                const uint32_t *o = (fwd ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
+                b = o[0];
+                e = o[1];
+                sb = tr.src * g.n;
+            }
+            const uint32_t incl = wave_incl_scan(e - b);
+            const uint32_t total = shfl_u32(incl, kWave - 1);
+            if (total == 0) continue;
+            s_scan[wib][lane] = incl;
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t f0 = 0; f0 < total; f0 += kWave) {
+                const uint32_t f = f0 + (uint32_t)lane;
+                uint32_t lo = 0, hi = kWave - 1;   // owner: first lane whose inclusive count exceeds f
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_scan[wib][mid] > f) hi = mid;
+                    else lo = mid + 1;
+                }
+                const uint32_t bj = shfl_u32(b, (int)lo), sbj = shfl_u32(sb, (int)lo);
+                const uint32_t startj = lo ? s_scan[wib][lo - 1] : 0u;
+                uint32_t x = 0;
+                bool got = false;
+                if (f < total) {
+                    x = sbj + idx[bj + (f - startj)];
+                    got = alive[x] && !mark[x] && atomicExch(&mark[x], 1u) == 0u;
+                }
+                const uint64_t m = __ballot(got);
+                if (m) {
+                    const uint32_t k2 = (uint32_t)__popcll(m);
+                    unsigned long long at = 0;
+                    if (lane == 0) at = atomicAdd(tail, (unsigned long long)k2);
+                    at = shfl_u64(at, 0);
+                    const uint64_t pos = at + (uint64_t)__popcll(m & below);
+                    if (got && pos < rq.cap) nxt[pos] = x;
+                    if (lane == 0) claimed += k2;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    count_add(ctr, c);
+    count_add(ctr, claimed);
 }
 
-// the pivot (from k_pivot's best key) starts both searches
-__global__ void k_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw) {
+// the pivot (from k_pivot's best key) starts both searches: it is marked and
+// is frontier 0 of each direction (counter slot 0)
+__global__ void k_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, ReachQueues rq) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     const unsigned long long b = *best;
     if (!b) return;
     const uint32_t p = (uint32_t)(b & 0xFFFFFFFFull);
     fw[p] = 1;
     bw[p] = 1;
+    rq.q[0][0][0] = p;
+    rq.q[1][0][0] = p;
+    rq.cnt[0] = 1;
+    rq.cnt[3] = 1;
 }
 
 __global__ void k_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
@@ -361,26 +456,6 @@ constexpr int kCondGroupWords = (int)kCondChunkWords / kCondGroupLanes;
 constexpr int kCondPassWords = kCondGroupWords < 16 ? kCondGroupWords : 16;
 constexpr int kCondPasses = kCondGroupWords / kCondPassWords;
 static_assert(kCondNodes == (uint32_t)kWave, "one node per lane in the edge-parallel phases");
-
-__device__ __forceinline__ uint32_t shfl_u32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src, kWave); }
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src) {
-    return (uint64_t)shfl_u32((uint32_t)x, src) | ((uint64_t)shfl_u32((uint32_t)(x >> 32), src) << 32);
-}
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const int lane = __lane_id();
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)x, off, kWave);
-        if (lane >= off) x += y;
-    }
-    return x;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t y = (uint32_t)__shfl_xor((int)x, off, kWave);
-        x = y > x ? y : x;
-    }
-    return x;
-}
 
 // word offset of component c's row: in R, or (bit 63 set) in the answer
 // matrix for an aliased answer row (see comp_row)
@@ -863,14 +938,19 @@ hipError_t launch_pivot(const ProdGraph &g, const uint8_t *alive, unsigned long 
     return hipGetLastError();
 }
 
-hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
-                        const unsigned long long *prev, unsigned long long *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_reach, dim3(node_grid((uint64_t)g.nQ * g.n)), dim3(kBlock), 0, s, g, alive, fw, bw, prev, ctr);
+hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw, const ReachQueues &rq,
+                        uint32_t it, unsigned long long *ctr, hipStream_t s) {
+    // one wavefront per 64 frontier entries of either direction, at most
+    // 2 * ceil(N / 64) items
+    const uint64_t N = (uint64_t)g.nQ * g.n;
+    hipLaunchKernelGGL(k_reach, dim3(wave_grid(2 * ((N + kWave - 1) / kWave))), dim3(kBlock), 0, s, g, alive, fw, bw,
+                       rq, it, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, hipStream_t s) {
-    hipLaunchKernelGGL(k_pivot_seed, dim3(1), dim3(64), 0, s, best, fw, bw);
+hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, const ReachQueues &rq,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_pivot_seed, dim3(1), dim3(64), 0, s, best, fw, bw, rq);
     return hipGetLastError();
 }
 

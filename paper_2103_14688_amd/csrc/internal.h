@@ -167,11 +167,23 @@ struct ProdGraph {
 hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
                        unsigned long long *ctr, hipStream_t s);
 hipError_t launch_pivot(const ProdGraph &g, const uint8_t *alive, unsigned long long *best, hipStream_t s);
-// one sweep of forward/backward reachability from the pivot (marks in place)
-hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
-                        const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
-// the pivot in *best (k_pivot's key; 0 = none) starts both searches
-hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, hipStream_t s);
+// frontiers of the pivot searches: q[direction][parity] hold cap entries
+// each (direction 0 forward, 1 backward); cnt[3 * direction + k] is a ring
+// of three frontier sizes, zero before the first search launch
+struct ReachQueues {
+    uint32_t *q[2][2];
+    unsigned long long *cnt;
+    uint64_t cap;
+};
+// one level of forward/backward reachability from the pivot: expands the
+// frontiers of launch `it` (0, 1, ... in order), marks in place and counts
+// the nodes it claims into *ctr
+hipError_t launch_reach(const ProdGraph &g, const uint8_t *alive, uint32_t *fw, uint32_t *bw, const ReachQueues &rq,
+                        uint32_t it, unsigned long long *ctr, hipStream_t s);
+// the pivot in *best (k_pivot's key; 0 = none) starts both searches as
+// frontier 0
+hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint32_t *bw, const ReachQueues &rq,
+                             hipStream_t s);
 constexpr uint32_t kStripes = 16;           // in-degree counters per component
 // per-state flags of the condensed strategy: bit 0 box start, bit 1 the only
 // final state of its box (its single-member rows alias the answer), box id
