@@ -51,9 +51,11 @@ typedef struct cfpq_graph_s *cfpq_graph;
 typedef struct cfpq_rsm_s *cfpq_rsm;
 typedef struct cfpq_result_s *cfpq_result;
 
-/* Device-memory hooks.  alloc returns NULL on failure; free receives the
- * pointer and size that alloc produced.  Both are called with the stream the
- * memory is used on. */
+/* Device-memory hooks.  alloc returns NULL on failure, else memory aligned
+ * to 256 bytes (as hipMalloc's; a less aligned block is handed back to free
+ * and the call fails with CFPQ_ERR_OOM); free receives the pointer and size
+ * that alloc produced.  Both are called with the stream the memory is used
+ * on. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);

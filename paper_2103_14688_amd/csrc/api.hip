@@ -51,7 +51,14 @@ struct Alloc {
     }
     void *get(size_t bytes, hipStream_t s) const {
         if (!bytes) bytes = 8;
-        if (has) return a.alloc(bytes, (void *)s, a.ctx);
+        if (has) {
+            void *p = a.alloc(bytes, (void *)s, a.ctx);
+            if (p && ((uintptr_t)p & 255u)) {   // the kernels take whole aligned vectors
+                a.free(p, bytes, (void *)s, a.ctx);
+                return nullptr;
+            }
+            return p;
+        }
         void *p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
         return p;

@@ -87,9 +87,20 @@ __device__ __forceinline__ void for_succs(const ProdGraph &g, uint32_t p, F &&fn
 #define NODE_LOOP(N)                                                                        \
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < (N); p += gridDim.x * blockDim.x)
 
+// *ctr += the sum of c over the workgroup (every thread of a kBlock-thread
+// workgroup calls it): one atomic per workgroup, since atomics on one
+// address from thousands of wavefronts serialise
 __device__ __forceinline__ void count_add(unsigned long long *ctr, unsigned long long c) {
+    __shared__ unsigned long long s_part[kBlock / kWave];
     c = wsum(c);
-    if (__lane_id() == 0 && c) atomicAdd(ctr, c);
+    if (__lane_id() == 0) s_part[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int k = 0; k < kBlock / kWave; ++k) t += s_part[k];
+        if (t) atomicAdd(ctr, t);
+    }
 }
 
 __device__ __forceinline__ uint32_t shfl_u32(uint32_t x, int src) { return (uint32_t)__shfl((int)x, src, kWave); }
@@ -162,6 +173,9 @@ __global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *b
     if (__lane_id() == 0 && mine) atomicMax(best, mine);
 }
 
+constexpr uint32_t kReachStage = 256;   // claimed nodes staged per wavefront before an append
+static_assert(kReachStage >= kWave, "a step's claims fit the staging buffer");
+
 // Forward and backward reachability from the pivot inside the live nodes,
 // level by level: launch it expands frontier it of both directions (forward
 // along successors, backward along predecessors), 64 edges per step per
@@ -174,6 +188,7 @@ __global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *b
 __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *alive, uint32_t *fw, uint32_t *bw,
                                                   ReachQueues rq, uint32_t it, unsigned long long *ctr) {
     __shared__ uint32_t s_scan[kBlock / kWave][kWave];
+    __shared__ uint32_t s_out[kBlock / kWave][kReachStage];   // claimed nodes, appended in one go
     const uint32_t r0 = it % 3, r1 = (it + 1) % 3, r2 = (it + 2) % 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         rq.cnt[r2] = 0;
@@ -206,6 +221,20 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
             tb = fwd ? g.out_off[q] : g.in_off[q];
             te = fwd ? g.out_off[q + 1] : g.in_off[q + 1];
         }
+        // claimed nodes gather in s_out and go to the next frontier with one
+        // atomic on its size per kReachStage - kWave of them
+        uint32_t staged = 0;
+        auto flush = [&]() {
+            unsigned long long at = 0;
+            if (lane == 0) at = atomicAdd(tail, (unsigned long long)staged);
+            at = shfl_u64(at, 0);
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t i = (uint32_t)lane; i < staged; i += kWave)
+                if (at + i < rq.cap) nxt[at + i] = s_out[wib][i];
+            __builtin_amdgcn_wave_barrier();
+            claimed += lane == 0 ? staged : 0u;
+            staged = 0;
+        };
         const uint32_t ntr = wave_max_u32(te - tb);
         for (uint32_t k = 0; k < ntr; ++k) {
             uint32_t b = 0, e = 0, sb = 0;
@@ -240,17 +269,14 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
                 }
                 const uint64_t m = __ballot(got);
                 if (m) {
-                    const uint32_t k2 = (uint32_t)__popcll(m);
-                    unsigned long long at = 0;
-                    if (lane == 0) at = atomicAdd(tail, (unsigned long long)k2);
-                    at = shfl_u64(at, 0);
-                    const uint64_t pos = at + (uint64_t)__popcll(m & below);
-                    if (got && pos < rq.cap) nxt[pos] = x;
-                    if (lane == 0) claimed += k2;
+                    if (staged + kWave > kReachStage) flush();
+                    if (got) s_out[wib][staged + (uint32_t)__popcll(m & below)] = x;
+                    staged += (uint32_t)__popcll(m);
                 }
             }
             __builtin_amdgcn_wave_barrier();
         }
+        if (staged) flush();
     }
     count_add(ctr, claimed);
 }
@@ -360,18 +386,31 @@ __global__ void k_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found,
 // ----------------------------------------------------------------------------
 // size[c] := 1 if component c has more than one member.  The edges entering c
 // from other components are counted in kStripes counters, stripe chosen by
-// the source node, so that the many edges into one large component do not
-// all meet on one address: stripe[c*kStripes + x % kStripes] counts edges
-// x -> c.  pending[c] := number of non-zero stripes (filled by k_cond_roots).
+// the member node they enter, so that the many edges into one large
+// component do not all meet on one address: stripe[c*kStripes + y % kStripes]
+// counts edges x -> y with y in c and x outside it (one atomic per member
+// node).  pending[c] := number of non-zero stripes (filled by k_cond_roots).
 __global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, uint32_t *stripe) {
     const uint32_t N = g.nQ * g.n;
     NODE_LOOP(N) {
         const uint32_t c = scc[p];
         if (c != p) size[c] = 1;  // a second member: the component is not a singleton
-        for_preds(g, p, [&](uint32_t x) {
-            if (scc[x] != c) atomicAdd(&stripe[(uint64_t)c * kStripes + x % kStripes], 1u);
-            return true;
-        });
+        // in-edges from other components, four per step (independent loads)
+        uint32_t k = 0;
+        const uint32_t q = p / g.n, v = p - q * g.n;
+        for (uint32_t t = g.in_off[q]; t < g.in_off[q + 1]; ++t) {
+            const InTrans tr = g.in_tr[t];
+            const uint32_t *o = g.goff + (uint64_t)tr.sym * (g.n + 1) + v;
+            const uint32_t b = o[0], e = o[1], base = tr.src * g.n;
+            uint32_t i = b;
+            for (; i + 4 <= e; i += 4) {
+                const uint32_t x0 = base + g.gidx[i], x1 = base + g.gidx[i + 1], x2 = base + g.gidx[i + 2],
+                               x3 = base + g.gidx[i + 3];
+                k += (scc[x0] != c) + (scc[x1] != c) + (scc[x2] != c) + (scc[x3] != c);
+            }
+            for (; i < e; ++i) k += scc[base + g.gidx[i]] != c;
+        }
+        if (k) atomicAdd(&stripe[(uint64_t)c * kStripes + p % kStripes], k);
     }
 }
 
@@ -412,8 +451,14 @@ __global__ void k_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *st
     unsigned long long c = 0;
     NODE_LOOP(N) {
         if (scc[p] != p) continue;
+        static_assert(kStripes % 4 == 0, "stripes read four at a time");
+        const uint4 *st = reinterpret_cast<const uint4 *>(stripe + (uint64_t)p * kStripes);
         uint32_t nz = 0;
-        for (uint32_t k = 0; k < kStripes; ++k) nz += stripe[(uint64_t)p * kStripes + k] != 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kStripes / 4; ++k) {
+            const uint4 w = st[k];
+            nz += (w.x != 0) + (w.y != 0) + (w.z != 0) + (w.w != 0);
+        }
         pending[p] = nz;
         if (nz == 0) {
             lev[p] = 0;
@@ -456,6 +501,19 @@ constexpr int kCondGroupWords = (int)kCondChunkWords / kCondGroupLanes;
 constexpr int kCondPassWords = kCondGroupWords < 16 ? kCondGroupWords : 16;
 constexpr int kCondPasses = kCondGroupWords / kCondPassWords;
 static_assert(kCondNodes == (uint32_t)kWave, "one node per lane in the edge-parallel phases");
+
+// a single-member component's row word: written once, read by its
+// successors in later launches (CFPQ_COND_NT = 1: streaming stores)
+#ifndef CFPQ_COND_NT
+#define CFPQ_COND_NT 1
+#endif
+__device__ __forceinline__ void store_row_word(uint64_t *dst, uint64_t x) {
+#if CFPQ_COND_NT
+    __builtin_nontemporal_store(x, dst);
+#else
+    *dst = x;
+#endif
+}
 
 // word offset of component c's row: in R, or (bit 63 set) in the answer
 // matrix for an aliased answer row (see comp_row)
@@ -563,7 +621,7 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
             const uint32_t w = pass0 + k * kWave + lane;
             if (w < Pn) {
                 if (single)
-                    row[k * kWave + lane] = acc[k];
+                    store_row_word(&row[k * kWave + lane], acc[k]);
                 else if (acc[k])
                     atomicOr((unsigned long long *)&row[k * kWave + lane], acc[k]);
                 if (alias) pc += (unsigned long long)__popcll(acc[k]);
@@ -752,7 +810,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
                     if (seedN[q] && w == (vN[q] >> 6) - pass0) acc[q][kk] |= 1ull << (vN[q] & 63);
                     if (w < cw) {
                         if (sgN[q])
-                            row[w] = acc[q][kk];
+                            store_row_word(&row[w], acc[q][kk]);
                         else if (acc[q][kk])
                             atomicOr((unsigned long long *)&row[w], acc[q][kk]);
                         if (aliasN[q]) pc += (unsigned long long)__popcll(acc[q][kk]);
@@ -821,7 +879,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
                     const uint32_t w = hw0 + (uint32_t)(kk * kCondGroupLanes + gl);
                     if (w < cw) {
                         if (singlej)
-                            row[w] = acc[kk];
+                            store_row_word(&row[w], acc[kk]);
                         else if (acc[kk])
                             atomicOr((unsigned long long *)&row[w], acc[kk]);
                         if (alias) pc += (unsigned long long)__popcll(acc[kk]);
@@ -865,11 +923,11 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
                     sb = tr.src * g.n;
                 }
                 edge_walk(s_scan[wib], b, e, sb, cm, [&](uint32_t j, uint32_t ei, uint32_t sbj, uint32_t cj) {
-                    const uint32_t cx = scc[sbj + g.sidx[ei]];
-                    const uint32_t pj = (uint32_t)base + j;
+                    const uint32_t y = sbj + g.sidx[ei];
+                    const uint32_t cx = scc[y];
                     // the last edge of a stripe retires the stripe, the last
                     // stripe releases the component
-                    if (cx != cj && atomicSub(&indeg[(uint64_t)cx * kStripes + pj % kStripes], 1u) == 1u &&
+                    if (cx != cj && atomicSub(&indeg[(uint64_t)cx * kStripes + y % kStripes], 1u) == 1u &&
                         atomicSub(&pending[cx], 1u) == 1u) {
                         lev[cx] = L + 1;
                         ++released;
@@ -878,8 +936,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
             }
         }
     }
-    released = wsum(released);
-    if (lane == 0 && released) atomicAdd(ctr_next, released);
+    count_add(ctr_next, released);
     // box 0's answer pairs: one striped atomic per wavefront
     pairs0 = wsum(pairs0);
     if (lane == 0 && pairs0) atomicAdd(&box_pairs[wave % kWave], pairs0);
