@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -464,20 +465,57 @@ cfpq_status check_pair(const cfpq_graph_s *g, const cfpq_rsm_s *r) {
     return CFPQ_OK;
 }
 
+// Pinned host buffers for counter read-backs, kept in a process-wide pool:
+// allocating and freeing pinned memory per query costs more than a small
+// query's kernels.  The pool holds at most one buffer per query that ran at
+// the same time and keeps them until the process ends (it is never torn
+// down, so no HIP call runs during static destruction).
+class PinnedPool {
+    std::mutex m_;
+    std::vector<std::pair<unsigned long long *, size_t>> free_;
+
+  public:
+    static PinnedPool &get() {
+        static PinnedPool *pool = new PinnedPool;
+        return *pool;
+    }
+    bool take(size_t n, unsigned long long *&h, size_t &cap) {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            for (size_t i = 0; i < free_.size(); ++i)
+                if (free_[i].second >= n) {
+                    h = free_[i].first;
+                    cap = free_[i].second;
+                    free_[i] = free_.back();
+                    free_.pop_back();
+                    return true;
+                }
+        }
+        unsigned long long *p = nullptr;
+        if (hipHostMalloc((void **)&p, n * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+            return false;
+        h = p;
+        cap = n;
+        return true;
+    }
+    void put(unsigned long long *h, size_t cap) {
+        std::lock_guard<std::mutex> lk(m_);
+        free_.emplace_back(h, cap);
+    }
+};
+
 struct PinnedCounters {
     unsigned long long *h = nullptr;
     size_t cap = 0;
     ~PinnedCounters() {
-        if (h) (void)hipHostFree(h);
+        if (h) PinnedPool::get().put(h, cap);
     }
     bool ensure(size_t n) {
         if (n <= cap) return true;
-        if (h) (void)hipHostFree(h);
+        if (h) PinnedPool::get().put(h, cap);
         h = nullptr;
         cap = 0;
-        if (hipHostMalloc((void **)&h, n * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) return false;
-        cap = n;
-        return true;
+        return PinnedPool::get().take(n, h, cap);
     }
 };
 

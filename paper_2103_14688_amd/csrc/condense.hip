@@ -170,7 +170,14 @@ __global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *b
         const unsigned long long o = __shfl_xor(mine, off, kWave);
         mine = o > mine ? o : mine;
     }
-    if (__lane_id() == 0 && mine) atomicMax(best, mine);
+    // one atomic per workgroup
+    __shared__ unsigned long long s_best[kBlock / kWave];
+    if (__lane_id() == 0) s_best[threadIdx.x / kWave] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / kWave; ++k) mine = s_best[k] > mine ? s_best[k] : mine;
+        if (mine) atomicMax(best, mine);
+    }
 }
 
 constexpr uint32_t kReachStage = 256;   // claimed nodes staged per wavefront before an append
@@ -434,12 +441,36 @@ __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t
 __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts,
                             const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz, uint32_t nch,
                             const uint64_t *mask) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (uint64_t)n_starts * n;
-         i += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = starts[i / n], u = (uint32_t)(i % n);
-        if (mask && !mask_bit(mask, u)) continue;
-        const uint32_t c = scc[s * n + u];
-        if (multi[c]) {
+    const int lane = __lane_id();
+    const uint64_t total = (uint64_t)n_starts * n;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - (uint64_t)lane; i0 < total;
+         i0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t i = i0 + (uint64_t)lane;
+        uint32_t c = 0, u = 0;
+        bool on = false;
+        if (i < total) {
+            const uint32_t s = starts[i / n];
+            u = (uint32_t)(i % n);
+            if (!mask || mask_bit(mask, u)) {
+                c = scc[s * n + u];
+                on = multi[c] != 0;
+            }
+        }
+        const uint64_t act = __ballot(on);
+        if (!act) continue;
+        // the lanes that hit the first active lane's word (usually all of
+        // them: the giant component's row) combine into one atomic
+        const int l0 = __ffsll((unsigned long long)act) - 1;
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)c, l0);
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)(u >> 6), l0);
+        const bool same = on && c == c0 && (u >> 6) == w0;
+        uint64_t bits = same ? 1ull << (u & 63) : 0ull;
+        for (int off = 32; off > 0; off >>= 1) bits |= shfl_u64(bits, lane ^ off);
+        if (lane == l0) {
+            atomicOr((unsigned long long *)&R[(uint64_t)c0 * P + w0], bits);
+            nz[(uint64_t)c0 * nch + w0 / (kCondChunks * kWave)] = 1;
+        }
+        if (on && !same) {
             atomicOr((unsigned long long *)&R[(uint64_t)c * P + (u >> 6)], 1ull << (u & 63));
             nz[(uint64_t)c * nch + (u >> 6) / (kCondChunks * kWave)] = 1;
         }
