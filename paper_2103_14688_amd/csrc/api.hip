@@ -941,7 +941,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     const uint64_t Nu = ((uint64_t)N + 1) / 2 * 2;         // u32 arrays start on 8-byte boundaries
     constexpr uint32_t kCtr = 8192;
     if ((uint64_t)nB * kSlotWords > kCtr) return fail(CFPQ_ERR_LIMIT, "too many boxes for the condensed strategy");
-    const uint32_t nch = (Pn + kCondChunkWords - 1) / kCondChunkWords;
+    const uint32_t nch = cond_chunks(Pn);
     const uint64_t nzb = ((uint64_t)N * nch + 63) / 64 * 64;   // non-empty chunk flags
 
     DevBuf T, dNT, dnt_act, u32s, u8s, ctr;

@@ -24,7 +24,7 @@ namespace cfpq {
 
 namespace {
 
-constexpr int kCondChunks = 8;
+constexpr int kCondChunks = CFPQ_COND_LANE_WORDS;   // words per lane of a chunk
 constexpr uint32_t kCondNodes = 64;   // consecutive nodes per work item (ballot-selected)
 static_assert(kCondChunks * kWave == kCondChunkWords, "chunk flags cover kCondChunks wavefront-widths");
 
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t
 // topological level is processed)
 __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts,
                             const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz, uint32_t nch,
-                            const uint64_t *mask) {
+                            uint32_t cwds, const uint64_t *mask) {
     const int lane = __lane_id();
     const uint64_t total = (uint64_t)n_starts * n;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - (uint64_t)lane; i0 < total;
@@ -468,11 +468,11 @@ __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint
         for (int off = 32; off > 0; off >>= 1) bits |= shfl_u64(bits, lane ^ off);
         if (lane == l0) {
             atomicOr((unsigned long long *)&R[(uint64_t)c0 * P + w0], bits);
-            nz[(uint64_t)c0 * nch + w0 / (kCondChunks * kWave)] = 1;
+            nz[(uint64_t)c0 * nch + w0 / cwds] = 1;
         }
         if (on && !same) {
             atomicOr((unsigned long long *)&R[(uint64_t)c * P + (u >> 6)], 1ull << (u & 63));
-            nz[(uint64_t)c * nch + (u >> 6) / (kCondChunks * kWave)] = 1;
+            nz[(uint64_t)c * nch + (u >> 6) / cwds] = 1;
         }
     }
 }
@@ -531,6 +531,8 @@ constexpr int kCondGroupWords = (int)kCondChunkWords / kCondGroupLanes;
 // words per lane and pass of the OR loop (register budget)
 constexpr int kCondPassWords = kCondGroupWords < 16 ? kCondGroupWords : 16;
 constexpr int kCondPasses = kCondGroupWords / kCondPassWords;
+static_assert(kCondPasses * kCondPassWords == kCondGroupWords, "whole passes per chunk");
+static_assert(CFPQ_COND_PAIR == 0 || kCondPasses == 1, "the paired row phase takes a chunk in one pass");
 static_assert(kCondNodes == (uint32_t)kWave, "one node per lane in the edge-parallel phases");
 
 // a single-member component's row word: written once, read by its
@@ -593,8 +595,9 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
                                 unsigned long long *box_pairs, unsigned long long &pairs0,
                                 unsigned long long &words_w, unsigned long long &words_r) {
     const int lane = __lane_id();
-    const uint32_t pass0 = ch * kCondChunkWords;
-    const uint32_t cw = (Pn - pass0 < kCondChunkWords) ? Pn - pass0 : kCondChunkWords;
+    const uint32_t cwds = cond_chunk_words(Pn);
+    const uint32_t pass0 = ch * cwds;
+    const uint32_t cw = (Pn - pass0 < cwds) ? Pn - pass0 : cwds;
     const bool single = multi[c] == 0;
     const uint32_t q = p / g.n, v = p - q * g.n;
     const uint32_t fq = flags[q];
@@ -630,7 +633,7 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 #pragma unroll
                 for (int k = 0; k < kCondChunks; ++k) {
                     const uint32_t w = pass0 + k * kWave + lane;
-                    if (w < Pn) acc[k] |= src[k * kWave + lane];
+                    if (w < pass0 + cw) acc[k] |= src[k * kWave + lane];
                 }
             }
         }
@@ -639,7 +642,7 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 #pragma unroll
     for (int k = 0; k < kCondChunks; ++k) {
         const uint32_t w = pass0 + k * kWave + lane;
-        if (w == seed_w) acc[k] |= seed_word;
+        if (w == seed_w && w < pass0 + cw) acc[k] |= seed_word;
         nonzero |= acc[k] != 0;
     }
     // a chunk that stays empty is neither written nor read later -- except
@@ -650,7 +653,7 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 #pragma unroll
         for (int k = 0; k < kCondChunks; ++k) {
             const uint32_t w = pass0 + k * kWave + lane;
-            if (w < Pn) {
+            if (w < pass0 + cw) {
                 if (single)
                     store_row_word(&row[k * kWave + lane], acc[k]);
                 else if (acc[k])
@@ -706,14 +709,14 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
     const int grp = lane / kCondGroupLanes, gl = lane % kCondGroupLanes;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    const uint32_t nch = (Pn + kCondChunkWords - 1) / kCondChunkWords;
+    const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
     const uint64_t items = (((uint64_t)N + kCondNodes - 1) / kCondNodes) * nch;
     unsigned long long released = 0, pairs0 = 0, words_w = 0, words_r = 0;
     for (uint64_t it = wave; it < items; it += nwaves) {
         const uint64_t base = (it / nch) * kCondNodes;
         const uint32_t ch = (uint32_t)(it % nch);
-        const uint32_t pass0 = ch * kCondChunkWords;
-        const uint32_t cw = (Pn - pass0 < kCondChunkWords) ? Pn - pass0 : kCondChunkWords;  // words in chunk
+        const uint32_t pass0 = ch * cwds;
+        const uint32_t cw = (Pn - pass0 < cwds) ? Pn - pass0 : cwds;  // words in chunk
         const uint32_t mine = (uint32_t)(base + lane);
         uint32_t cm = 0;
         bool at = false;
@@ -986,7 +989,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
 // copy each component's row to its other members (closure blocks on request)
 __global__ __launch_bounds__(kBlock) void k_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc,
                                                         const uint8_t *nz, uint64_t *T) {
-    const uint32_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
+    const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
     const int lane = __lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -995,7 +998,7 @@ __global__ __launch_bounds__(kBlock) void k_cond_expand(uint32_t N, uint32_t P, 
         const uint64_t *src = T + (uint64_t)c * P;
         uint64_t *dst = T + pp * P;
         for (uint32_t w = lane; w < Pn; w += kWave) {
-            const bool live = nz[(uint64_t)c * nch + w / (kCondChunks * kWave)] != 0;
+            const bool live = nz[(uint64_t)c * nch + w / cwds] != 0;
             if (c != pp || !live) dst[w] = live ? src[w] : 0ull;
         }
     }
@@ -1089,10 +1092,10 @@ hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, co
                             uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
                             const uint64_t *mask, hipStream_t s) {
     const uint64_t N = (uint64_t)nQ * n;
-    const uint32_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
+    const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
     hipLaunchKernelGGL(k_cond_zero_multi, dim3(wave_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R);
     hipLaunchKernelGGL(k_cond_seed, dim3(node_grid((uint64_t)n * n_starts)), dim3(kBlock), 0, s, n, P, starts,
-                       n_starts, scc, multi, R, nz, nch, mask);
+                       n_starts, scc, multi, R, nz, nch, cwds, mask);
     return hipGetLastError();
 }
 
@@ -1108,7 +1111,7 @@ hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const 
                              unsigned long long *ctr_next, unsigned long long *ctr_clear, unsigned long long *box_pairs,
                              unsigned long long *bytes_ctr, hipStream_t s) {
     const uint64_t N = (uint64_t)g.nQ * g.n;
-    const uint64_t nch = (Pn + kCondChunks * kWave - 1) / (kCondChunks * kWave);
+    const uint64_t nch = cond_chunks(Pn);
     hipLaunchKernelGGL(k_cond_level, dim3(wave_grid((N + kCondNodes - 1) / kCondNodes * nch)), dim3(kBlock), 0, s, g, P,
                        Pn, scc,
                        multi, indeg, pending, lev, R, NT, nz, flags, L, ctr_prev, ctr_next, ctr_clear, box_pairs,

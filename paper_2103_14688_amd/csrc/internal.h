@@ -217,7 +217,20 @@ hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const 
                              unsigned long long *bytes_ctr, hipStream_t s);
 hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint8_t *nz, uint64_t *T,
                               hipStream_t s);
-constexpr uint32_t kCondChunkWords = 512;   // chunk of a component row with its own non-empty flag
+// A component row is cut into cond_chunks(Pn) equal chunks of at most
+// kCondChunkWords words, each with its own non-empty flag: at most
+// CFPQ_COND_LANE_WORDS words per lane of a wavefront (a compile-time tuning
+// parameter, at most 16; 9 measured fastest, ahead of 8, 13 and 16: equal
+// chunks avoid a short last chunk that costs a whole work item)
+#ifndef CFPQ_COND_LANE_WORDS
+#define CFPQ_COND_LANE_WORDS 9
+#endif
+constexpr uint32_t kCondChunkWords = CFPQ_COND_LANE_WORDS * 64;
+__host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) { return (Pn + kCondChunkWords - 1) / kCondChunkWords; }
+__host__ __device__ inline uint32_t cond_chunk_words(uint32_t Pn) {
+    const uint32_t c = cond_chunks(Pn);
+    return c ? (Pn + c - 1) / c : kCondChunkWords;
+}
 
 // Fused small-graph fixpoint: one workgroup runs a whole query.
 struct FusedQuery {

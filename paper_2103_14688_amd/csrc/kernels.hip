@@ -670,12 +670,13 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
     uint64_t *dnt = a.dNT ? a.dNT + ((uint64_t)N * a.n + v) * a.P : nullptr;
     bool any = false;
+    const uint32_t nch = cond_chunks(a.Pn), cwds = cond_chunk_words(a.Pn);
     for (uint32_t k = lane; k < a.Pn; k += kWave) {
         uint64_t acc = 0;
         for (uint32_t i = fb; i < fe; ++i) {
             const uint64_t node = (uint64_t)a.fin[i] * a.n + v;
             const uint64_t row = a.row_map ? (uint64_t)a.row_map[node] : node;
-            if (a.row_nz && !a.row_nz[row * ((a.Pn + kCondChunkWords - 1) / kCondChunkWords) + k / kCondChunkWords])
+            if (a.row_nz && !a.row_nz[row * nch + k / cwds])
                 continue;  // chunk never written: all zero
             acc |= a.T[row * a.P + k];
         }

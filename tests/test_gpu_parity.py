@@ -272,6 +272,26 @@ def test_rpq_bench_size_sampled_rows(strategy):
     assert res.count(0) == total == deltas[0] and it == 2
 
 
+@pytest.mark.parametrize("n", [36865, 74000])
+def test_rpq_sampled_rows_uneven_chunks(n):
+    # component rows of 577 and 1157 words: two and three equal chunks of a
+    # width that is not a multiple of the wavefront's 64 words
+    import oracle
+    g = synth.powerlaw(n, seed=synth.BASE_SEED + 5)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
+    _, _, res = run(g, R, strategy=cfpq.STRATEGY_CONDENSED)
+    bm = res.bitmap(0)
+    assert H.padding_clear(bm, g.n)
+    rng = np.random.default_rng(n)
+    srcs = np.sort(rng.choice(g.n, size=24, replace=False)).astype(np.uint32)
+    srcs = np.concatenate([srcs, np.array([0, g.n - 1], dtype=np.uint32)])
+    want = oracle.rpq_rows(g.n, g.src, g.lbl, g.dst, g.labels, synth.RPQ_C2, srcs, threads=8)
+    assert np.array_equal(bm[srcs], want)
+    _, _, lv = run(g, R, strategy=cfpq.STRATEGY_LEVELS)
+    assert np.array_equal(lv.bitmap(0), bm)
+    assert res.count(0) == int(np.unpackbits(bm.view(np.uint8)).sum())
+
+
 # ---------------------------------------------------------------------------
 # condensed closure (components of the product graph) on regular queries
 # ---------------------------------------------------------------------------
