@@ -103,28 +103,35 @@ def main():
         cfpq.query(graph, q, **kw).close()
     torch.cuda.synchronize()
 
-    results = []
+    # a steady query loop: each step's result is read (its statistics and
+    # per-kernel profile, host-side) and released when the next one exists,
+    # so its memory returns to the allocator's cache as a server's would
+    rows, last = [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        results.append(cfpq.query(graph, q, profile=True, **kw))
+        r = cfpq.query(graph, q, profile=True, **kw)
+        rows.append((r.stats(), r.profile(dominant), r.profile(cfpq.KERNEL_SEED), r.profile(cfpq.KERNEL_WRITEBACK),
+                     r.profile(cfpq.KERNEL_COND_SCC)))
+        if last is not None:
+            last.close()
+        last = r
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
-    pairs = results[-1].count(0)
-    it, deltas, fix_ms = results[-1].stats()
-    fix = [r.stats()[2] for r in results]
+    pairs = last.count(0)
+    it, deltas, fix_ms = rows[-1][0]
+    fix = [x[0][2] for x in rows]
     # dominant kernel: closure level launches, summed over the timed steps
     lv_n = lv_ms = lv_bytes = 0
-    for r in results:
-        n_l, ms_l, by_l = r.profile(dominant)
+    for x in rows:
+        n_l, ms_l, by_l = x[1]
         lv_n += n_l
         lv_ms += ms_l
         lv_bytes += by_l
-    seed = [r.profile(cfpq.KERNEL_SEED) for r in results]
-    wb = [r.profile(cfpq.KERNEL_WRITEBACK) for r in results]
-    scc = [r.profile(cfpq.KERNEL_COND_SCC) for r in results]
-    for r in results:
-        r.close()
+    seed = [x[2] for x in rows]
+    wb = [x[3] for x in rows]
+    scc = [x[4] for x in rows]
+    last.close()
     avg_launch_ms = lv_ms / max(lv_n, 1)
     bytes_per_launch = lv_bytes / max(lv_n, 1)
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if avg_launch_ms > 0 else 0.0

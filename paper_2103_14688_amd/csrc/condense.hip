@@ -306,7 +306,9 @@ __global__ void k_pivot_seed(const unsigned long long *best, uint32_t *fw, uint3
 }
 
 __global__ void k_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
-                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr) {
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr,
+                              const unsigned long long *open0, const unsigned long long *open1) {
+    if (open0 && (*open0 | *open1)) return;  // a search is not complete
     const unsigned long long b = *best;
     if (!b) return;
     const uint32_t pivot = (uint32_t)(b & 0xFFFFFFFFull);
@@ -399,7 +401,9 @@ __global__ void k_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found,
 // component do not all meet on one address: stripe[c*kStripes + y % kStripes]
 // counts edges x -> y with y in c and x outside it (one atomic per member
 // node).  pending[c] := number of non-zero stripes (filled by k_cond_roots).
-__global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, uint32_t *stripe) {
+__global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, uint32_t *stripe,
+                             const unsigned long long *skip_if) {
+    if (skip_if && *skip_if) return;
     const uint32_t N = g.nQ * g.n;
     NODE_LOOP(N) {
         const uint32_t c = scc[p];
@@ -426,7 +430,9 @@ __global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, u
 // rows of components with several members are accumulated with atomics:
 // clear them (one wavefront per representative)
 __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t P, uint32_t Pn, const uint32_t *scc,
-                                                            const uint32_t *multi, uint64_t *R) {
+                                                            const uint32_t *multi, uint64_t *R,
+                                                            const unsigned long long *skip_if) {
+    if (skip_if && *skip_if) return;
     const int lane = __lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
@@ -442,7 +448,8 @@ __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t
 // topological level is processed)
 __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint32_t n_starts,
                             const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz, uint32_t nch,
-                            uint32_t cwds, const uint64_t *mask) {
+                            uint32_t cwds, const uint64_t *mask, const unsigned long long *skip_if) {
+    if (skip_if && *skip_if) return;
     const int lane = __lane_id();
     const uint64_t total = (uint64_t)n_starts * n;
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - (uint64_t)lane; i0 < total;
@@ -480,7 +487,8 @@ __global__ void k_cond_seed(uint32_t n, uint32_t P, const uint32_t *starts, uint
 }
 
 __global__ void k_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *stripe, uint32_t *pending,
-                             uint32_t *lev, unsigned long long *ctr) {
+                             uint32_t *lev, unsigned long long *ctr, const unsigned long long *skip_if) {
+    if (skip_if && *skip_if) return;
     unsigned long long c = 0;
     NODE_LOOP(N) {
         if (scc[p] != p) continue;
@@ -708,7 +716,7 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
     const uint32_t N = g.nQ * g.n;
     const int lane = __lane_id();
     const uint32_t wib = threadIdx.x / kWave;
-    const int grp = lane / kCondGroupLanes, gl = lane % kCondGroupLanes;
+    [[maybe_unused]] const int grp = lane / kCondGroupLanes, gl = lane % kCondGroupLanes;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
@@ -1066,8 +1074,10 @@ hipError_t launch_pivot_seed(const unsigned long long *best, uint32_t *fw, uint3
 }
 
 hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
-                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_fwbw_assign, dim3(node_grid(N)), dim3(kBlock), 0, s, N, alive, fw, bw, best, scc, ctr);
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr,
+                              const unsigned long long *open0, const unsigned long long *open1, hipStream_t s) {
+    hipLaunchKernelGGL(k_fwbw_assign, dim3(node_grid(N)), dim3(kBlock), 0, s, N, alive, fw, bw, best, scc, ctr, open0,
+                       open1);
     return hipGetLastError();
 }
 
@@ -1103,25 +1113,28 @@ hipError_t launch_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found,
 }
 
 hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *size, uint32_t *stripe,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_cond_count, dim3(node_grid((uint64_t)g.nQ * g.n)), dim3(kBlock), 0, s, g, scc, size, stripe);
+                             const unsigned long long *skip_if, hipStream_t s) {
+    hipLaunchKernelGGL(k_cond_count, dim3(node_grid((uint64_t)g.nQ * g.n)), dim3(kBlock), 0, s, g, scc, size, stripe,
+                       skip_if);
     return hipGetLastError();
 }
 
 hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, const uint32_t *starts,
                             uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
-                            const uint64_t *mask, hipStream_t s) {
+                            const uint64_t *mask, const unsigned long long *skip_if, hipStream_t s) {
     const uint64_t N = (uint64_t)nQ * n;
     const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
-    hipLaunchKernelGGL(k_cond_zero_multi, dim3(wave_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R);
+    hipLaunchKernelGGL(k_cond_zero_multi, dim3(wave_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R,
+                       skip_if);
     hipLaunchKernelGGL(k_cond_seed, dim3(node_grid((uint64_t)n * n_starts)), dim3(kBlock), 0, s, n, P, starts,
-                       n_starts, scc, multi, R, nz, nch, cwds, mask);
+                       n_starts, scc, multi, R, nz, nch, cwds, mask, skip_if);
     return hipGetLastError();
 }
 
 hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *stripe, uint32_t *pending,
-                             uint32_t *lev, unsigned long long *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(k_cond_roots, dim3(node_grid(N)), dim3(kBlock), 0, s, N, scc, stripe, pending, lev, ctr);
+                             uint32_t *lev, unsigned long long *ctr, const unsigned long long *skip_if, hipStream_t s) {
+    hipLaunchKernelGGL(k_cond_roots, dim3(node_grid(N)), dim3(kBlock), 0, s, N, scc, stripe, pending, lev, ctr,
+                       skip_if);
     return hipGetLastError();
 }
 

@@ -104,6 +104,7 @@ struct WritebackArgs {
     const uint8_t *row_nz;         // optional: per (T row, 512-word chunk) flag; 0 = the chunk is all zero
     const uint32_t *state_flags;   // optional (with multi): rows of single-member components of a
     const uint32_t *multi;         //   kAliasFinal state are already in NT; such rows are skipped
+    const unsigned long long *skip_if[2];   // optional: the launch does nothing if either is nonzero
 };                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip
@@ -192,8 +193,11 @@ constexpr uint32_t kStartState = 1, kAliasFinal = 2, kFlagBoxShift = 2;
 // counters of the condensed levels: kWave stripes of answer pairs per box,
 // then (at kBytesSlot) kWave (words written, predecessor words requested) pairs
 constexpr uint32_t kBytesSlot = 4096;
+// open0/open1 (optional): the searches' next frontier sizes; nonzero means
+// they are not complete and the launch does nothing
 hipError_t launch_fwbw_assign(uint32_t N, uint8_t *alive, const uint32_t *fw, const uint32_t *bw,
-                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr, hipStream_t s);
+                              const unsigned long long *best, uint32_t *scc, unsigned long long *ctr,
+                              const unsigned long long *open0, const unsigned long long *open1, hipStream_t s);
 hipError_t launch_color_init(uint32_t N, const uint8_t *alive, uint32_t *color, uint8_t *found, hipStream_t s);
 hipError_t launch_color_prop(const ProdGraph &g, const uint8_t *alive, uint32_t *color,
                              const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
@@ -203,13 +207,15 @@ hipError_t launch_color_back(const ProdGraph &g, const uint8_t *alive, const uin
                              uint32_t *scc, const unsigned long long *prev, unsigned long long *ctr, hipStream_t s);
 hipError_t launch_color_remove(uint32_t N, uint8_t *alive, const uint8_t *found, unsigned long long *ctr,
                                hipStream_t s);
+// skip_if (optional, the condensation set-up kernels): the launch does
+// nothing when *skip_if is nonzero (nodes still without a component)
 hipError_t launch_cond_count(const ProdGraph &g, const uint32_t *scc, uint32_t *size, uint32_t *stripe,
-                             hipStream_t s);
+                             const unsigned long long *skip_if, hipStream_t s);
 hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, const uint32_t *starts,
                             uint32_t n_starts, const uint32_t *scc, const uint32_t *multi, uint64_t *R, uint8_t *nz,
-                            const uint64_t *mask, hipStream_t s);
+                            const uint64_t *mask, const unsigned long long *skip_if, hipStream_t s);
 hipError_t launch_cond_roots(uint32_t N, const uint32_t *scc, const uint32_t *stripe, uint32_t *pending,
-                             uint32_t *lev, unsigned long long *ctr, hipStream_t s);
+                             uint32_t *lev, unsigned long long *ctr, const unsigned long long *skip_if, hipStream_t s);
 hipError_t launch_cond_level(const ProdGraph &g, uint32_t P, uint32_t Pn, const uint32_t *scc, const uint32_t *multi,
                              uint32_t *indeg, uint32_t *pending, uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
                              const uint32_t *flags, uint32_t L, const unsigned long long *ctr_prev,

@@ -702,6 +702,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
 }
 
 __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
+    if ((a.skip_if[0] && *a.skip_if[0]) || (a.skip_if[1] && *a.skip_if[1])) return;
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
     const int lane = __lane_id();
@@ -965,7 +966,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
     wb.T = Q.T; wb.NT = Q.NT; wb.dNT = Q.dNT; wb.dnt_act = Q.dnt_act; wb.rank = Q.rank;
     wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr; wb.fresh = 0; wb.row_nz = nullptr;
-    wb.state_flags = nullptr; wb.multi = nullptr;
+    wb.state_flags = nullptr; wb.multi = nullptr; wb.skip_if[0] = wb.skip_if[1] = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     const bool narrow = Q.Pn <= kNarrowWords;

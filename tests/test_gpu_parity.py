@@ -325,6 +325,39 @@ def test_condensed_cycles_and_chains(text):
             check_box(res, want, g.n)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_condensed_repeated_queries_on_one_graph(seed):
+    # the first query on a graph handle sizes the launch chains; later ones go
+    # out in one piece with those sizes and finish synchronously from the
+    # first step the sizes did not cover (searches, colouring, levels)
+    rng = np.random.default_rng(9100 + seed)
+    labels = [f"l{i}" for i in range(5)]
+    n = int(rng.integers(300, 4000))
+    g = synth.powerlaw(n, labels=tuple(labels), mean_deg=float(rng.uniform(0.7, 4)), seed=seed + 40)
+    graph = cfpq.Graph.from_synth(g)
+    texts = [synth.random_regex(rng, [str(x) for x in rng.choice(labels, size=4, replace=False)]) for _ in range(4)]
+    want = {t: H.oracle_regex(g, t) for t in texts}
+    for text in texts + texts[::-1] + texts:
+        res = cfpq.query(graph, cfpq.Query(rsm_mod.from_regex(text, g.labels)), strategy=cfpq.STRATEGY_CONDENSED)
+        check_box(res, want[text], g.n)
+        assert res.stats()[0] == 2
+
+
+def test_condensed_repeated_queries_deep_and_shallow():
+    # one handle: a shallow query, then a 5000-level chain and a 9500-node
+    # ring (chain sizes far too short), then shallow again
+    chain = [(i, "a" if i % 3 else "b", i + 1) for i in range(4999)]
+    ring = [(5000 + i, "a", 5000 + (i + 1) % 9500) for i in range(9500)]
+    loops = [(i, "b", i) for i in range(0, 14500, 97)]
+    g = synth.make_graph(14500, chain + ring + loops, ["a", "b"])
+    graph = cfpq.Graph.from_synth(g)
+    texts = ["b", "a*", "(a | b)+", "b", "a b a", "(a b)* | b", "b"]
+    want = {t: H.oracle_regex(g, t) for t in set(texts)}
+    for text in texts:
+        res = cfpq.query(graph, cfpq.Query(rsm_mod.from_regex(text, g.labels)), strategy=cfpq.STRATEGY_CONDENSED)
+        check_box(res, want[text], g.n)
+
+
 def test_condensed_rejects_grammars():
     g = synth.chain("aabb")
     graph = cfpq.Graph.from_synth(g)
