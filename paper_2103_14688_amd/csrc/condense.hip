@@ -433,13 +433,19 @@ __global__ __launch_bounds__(kBlock) void k_cond_zero_multi(uint32_t N, uint32_t
                                                             const uint32_t *multi, uint64_t *R,
                                                             const unsigned long long *skip_if) {
     if (skip_if && *skip_if) return;
+    // a lane per node finds the representatives (few), then the wavefront
+    // clears their rows one after another
     const int lane = __lane_id();
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t p = wave; p < N; p += nwaves) {
-        if (scc[p] != p || !multi[p]) continue;
-        uint64_t *row = R + p * P;
-        for (uint32_t w = lane; w < Pn; w += kWave) row[w] = 0;
+    for (uint64_t p0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x - (uint64_t)lane; p0 < N;
+         p0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = p0 + (uint64_t)lane;
+        uint64_t todo = __ballot(p < N && scc[p] == p && multi[p] != 0);
+        while (todo) {
+            const int j = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            uint64_t *row = R + (p0 + (uint64_t)j) * P;
+            for (uint32_t w = lane; w < Pn; w += kWave) row[w] = 0;
+        }
     }
 }
 
@@ -1124,7 +1130,7 @@ hipError_t launch_cond_seed(uint32_t n, uint32_t P, uint32_t Pn, uint32_t nQ, co
                             const uint64_t *mask, const unsigned long long *skip_if, hipStream_t s) {
     const uint64_t N = (uint64_t)nQ * n;
     const uint32_t nch = cond_chunks(Pn), cwds = cond_chunk_words(Pn);
-    hipLaunchKernelGGL(k_cond_zero_multi, dim3(wave_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R,
+    hipLaunchKernelGGL(k_cond_zero_multi, dim3(node_grid(N)), dim3(kBlock), 0, s, (uint32_t)N, P, Pn, scc, multi, R,
                        skip_if);
     hipLaunchKernelGGL(k_cond_seed, dim3(node_grid((uint64_t)n * n_starts)), dim3(kBlock), 0, s, n, P, starts,
                        n_starts, scc, multi, R, nz, nch, cwds, mask, skip_if);

@@ -708,18 +708,13 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
     const int lane = __lane_id();
     const uint64_t wave = gtid >> 6, nwaves = gthreads >> 6;
     const uint64_t rows = (uint64_t)a.nB * a.n;
-    for (uint64_t r = wave; r < rows; r += nwaves) {
+    auto one_row = [&](uint64_t r) {
         const uint32_t N = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
         if (a.fin_off[N] == a.fin_off[N + 1]) {
             // a box without final states derives nothing: its relation is empty
             if (a.fresh)
                 for (uint32_t k = lane; k < a.Pn; k += kWave) a.NT[((uint64_t)N * a.n + v) * a.P + k] = 0;
-            continue;
-        }
-        if (a.state_flags) {
-            const uint32_t f = a.fin[a.fin_off[N]];
-            if ((a.state_flags[f] & kAliasFinal) && a.multi[a.row_map[(uint64_t)f * a.n + v]] == 0)
-                continue;  // written (and counted) by the closure itself
+            return;
         }
         unsigned long long c = 0;
         bool any = false;
@@ -730,6 +725,26 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
                 atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
             atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
         }
+    };
+    if (!a.state_flags) {
+        for (uint64_t r = wave; r < rows; r += nwaves) one_row(r);
+        return;
+    }
+    // condensed closure: most answer rows were written (and counted) by the
+    // closure itself; a lane per row finds the others, 64 rows at a time
+    for (uint64_t r0 = wave * kWave; r0 < rows; r0 += nwaves * kWave) {
+        const uint64_t r = r0 + (uint64_t)lane;
+        bool need = false;
+        if (r < rows) {
+            const uint32_t N = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
+            need = true;
+            if (a.fin_off[N] != a.fin_off[N + 1]) {
+                const uint32_t f = a.fin[a.fin_off[N]];
+                if ((a.state_flags[f] & kAliasFinal) && a.multi[a.row_map[(uint64_t)f * a.n + v]] == 0) need = false;
+            }
+        }
+        for (uint64_t todo = __ballot(need); todo; todo &= todo - 1)
+            one_row(r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1));
     }
 }
 
