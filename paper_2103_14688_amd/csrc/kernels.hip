@@ -26,6 +26,33 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
     return x;
 }
 
+// ctr_k += the workgroup's sum of v_k, k < 3 (null counters are skipped;
+// every thread of a kBlock-thread workgroup calls it): one atomic per counter
+// and workgroup, since atomics on one address from thousands of wavefronts
+// serialise
+__device__ __forceinline__ void block_add(unsigned long long *c0, unsigned long long v0,
+                                          unsigned long long *c1 = nullptr, unsigned long long v1 = 0,
+                                          unsigned long long *c2 = nullptr, unsigned long long v2 = 0) {
+    __shared__ unsigned long long s_part[3][kBlock / kWave];
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    v2 = wave_sum(v2);
+    const uint32_t w = threadIdx.x / kWave;
+    if (__lane_id() == 0) {
+        s_part[0][w] = v0;
+        s_part[1][w] = v1;
+        s_part[2][w] = v2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int k = 0; k < kBlock / kWave; ++k) t += s_part[threadIdx.x][k];
+        unsigned long long *c = threadIdx.x == 0 ? c0 : (threadIdx.x == 1 ? c1 : c2);
+        if (t && c) atomicAdd(c, t);
+    }
+}
+
 __device__ __forceinline__ bool test_bit(const uint64_t *bits, uint32_t i) {
     return (bits[i >> 6] >> (i & 63)) & 1ull;
 }
@@ -641,13 +668,9 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
         }
         fed_rows += fed ? 1 : 0;
     }
-    cnt = wave_sum(cnt);
-    if (lane == 0) {
-        unsigned long long *c = a.ctr + (uint64_t)a.slot_cur * kSlotWords;
-        if (cnt) atomicAdd(&c[0], cnt);
-        if (fed_rows) atomicAdd(&c[1], fed_rows);
-        if (new_rows) atomicAdd(&c[2], new_rows);
-    }
+    // new bits per lane; rows fed and rows gaining bits once per wavefront
+    unsigned long long *c = a.ctr + (uint64_t)a.slot_cur * kSlotWords;
+    block_add(&c[0], cnt, &c[1], lane == 0 ? fed_rows : 0ull, &c[2], lane == 0 ? new_rows : 0ull);
 }
 
 hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s) {
@@ -701,8 +724,17 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     any_row = __ballot(any) != 0;
 }
 
+constexpr uint32_t kWbLdsBoxes = 64;   // boxes whose new-edge counts gather in LDS first
+
 __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
     if ((a.skip_if[0] && *a.skip_if[0]) || (a.skip_if[1] && *a.skip_if[1])) return;
+    // new edges per box: summed per workgroup in LDS (rows of one box meet
+    // on one counter), flushed with one atomic per box and workgroup
+    __shared__ unsigned long long s_box[kWbLdsBoxes];
+    const bool lds_boxes = a.nB <= kWbLdsBoxes;
+    if (lds_boxes)
+        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x) s_box[i] = 0;
+    __syncthreads();
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
     const int lane = __lane_id();
@@ -723,16 +755,17 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
         if (lane == 0 && any) {
             if (a.dnt_act)
                 atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
-            atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
+            if (lds_boxes)
+                atomicAdd(&s_box[N], c);
+            else
+                atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
         }
     };
-    if (!a.state_flags) {
+    if (!a.state_flags)
         for (uint64_t r = wave; r < rows; r += nwaves) one_row(r);
-        return;
-    }
     // condensed closure: most answer rows were written (and counted) by the
     // closure itself; a lane per row finds the others, 64 rows at a time
-    for (uint64_t r0 = wave * kWave; r0 < rows; r0 += nwaves * kWave) {
+    for (uint64_t r0 = wave * kWave; a.state_flags && r0 < rows; r0 += nwaves * kWave) {
         const uint64_t r = r0 + (uint64_t)lane;
         bool need = false;
         if (r < rows) {
@@ -745,6 +778,11 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
         }
         for (uint64_t todo = __ballot(need); todo; todo &= todo - 1)
             one_row(r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1));
+    }
+    if (lds_boxes) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x)
+            if (s_box[i]) atomicAdd(&a.ctr[(uint64_t)(a.slot_base + i) * kSlotWords], s_box[i]);
     }
 }
 
@@ -763,8 +801,7 @@ __global__ void k_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uin
     unsigned long long c = 0;
     for (uint64_t i = gtid; i < rows * words; i += gthreads)
         c += (unsigned long long)__popcll(p[(i / words) * pitch + (i % words)]);
-    c = wave_sum(c);
-    if (__lane_id() == 0 && c) atomicAdd(out, c);
+    block_add(out, c);
 }
 
 hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
@@ -790,8 +827,7 @@ __global__ void k_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned lon
             h += splitmix64((u << 32) | v);
         }
     }
-    h = wave_sum(h);
-    if (__lane_id() == 0 && h) atomicAdd(out, h);
+    block_add(out, h);
 }
 
 hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned long long *out,
