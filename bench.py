@@ -34,7 +34,8 @@ PMC_TRAFFIC = {("cfpq-gfx950 0.1", "levels"): 3.4596e9,
                ("cfpq-gfx950 0.3", "auto"): 100.9e6, ("cfpq-gfx950 0.3", "condensed"): 100.9e6,
                ("cfpq-gfx950 0.4", "auto"): 101.0e6, ("cfpq-gfx950 0.4", "condensed"): 101.0e6,
                ("cfpq-gfx950 0.5", "auto"): 107.1e6, ("cfpq-gfx950 0.5", "condensed"): 107.1e6,
-               ("cfpq-gfx950 0.6", "auto"): 107.2e6, ("cfpq-gfx950 0.6", "condensed"): 107.2e6}
+               ("cfpq-gfx950 0.6", "auto"): 107.2e6, ("cfpq-gfx950 0.6", "condensed"): 107.2e6,
+               ("cfpq-gfx950 0.7", "auto"): 109.0e6, ("cfpq-gfx950 0.7", "condensed"): 109.0e6}
 
 
 def main():

@@ -2090,4 +2090,4 @@ extern "C" void cfpq_paths_close(cfpq_paths it) { delete it; }
 
 extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
 
-extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.6"; }
+extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.7"; }

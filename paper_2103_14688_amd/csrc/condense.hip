@@ -533,10 +533,11 @@ constexpr uint32_t kCondPredCap = 8;     // predecessor rows listed per node; mo
 // a compile-time tuning parameter
 // nodes per step of the row phase with a whole wavefront per node (their
 // row loads in flight together); 0 selects the lane-group path instead.
-// Compile-time tuning parameters: 2 measured fastest (3 and 4 cost
-// occupancy), ahead of lane groups of 16 or 32 lanes per node
+// Compile-time tuning parameters: with 13-word lanes one node per step
+// measured fastest (two cost the registers of a second accumulator; with
+// 8-word lanes two were fastest), ahead of lane groups of 16 or 32 lanes
 #ifndef CFPQ_COND_PAIR
-#define CFPQ_COND_PAIR 2
+#define CFPQ_COND_PAIR 1
 #endif
 #ifndef CFPQ_COND_GROUP_LANES
 #define CFPQ_COND_GROUP_LANES 64

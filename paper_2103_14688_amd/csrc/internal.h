@@ -226,10 +226,11 @@ hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_
 // A component row is cut into cond_chunks(Pn) equal chunks of at most
 // kCondChunkWords words, each with its own non-empty flag: at most
 // CFPQ_COND_LANE_WORDS words per lane of a wavefront (a compile-time tuning
-// parameter, at most 16; 9 measured fastest, ahead of 8, 13 and 16: equal
-// chunks avoid a short last chunk that costs a whole work item)
+// parameter, at most 16; with one node per step 13 measured fastest, ahead
+// of 8, 9 and 16: equal chunks avoid a short last chunk that costs a whole
+// work item, and fewer chunks repeat the predecessor listing less often)
 #ifndef CFPQ_COND_LANE_WORDS
-#define CFPQ_COND_LANE_WORDS 9
+#define CFPQ_COND_LANE_WORDS 13
 #endif
 constexpr uint32_t kCondChunkWords = CFPQ_COND_LANE_WORDS * 64;
 __host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) { return (Pn + kCondChunkWords - 1) / kCondChunkWords; }

@@ -272,10 +272,10 @@ def test_rpq_bench_size_sampled_rows(strategy):
     assert res.count(0) == total == deltas[0] and it == 2
 
 
-@pytest.mark.parametrize("n", [36865, 74000])
+@pytest.mark.parametrize("n", [36865, 74000, 110000])
 def test_rpq_sampled_rows_uneven_chunks(n):
-    # component rows of 577 and 1157 words: two and three equal chunks of a
-    # width that is not a multiple of the wavefront's 64 words
+    # component rows of 577, 1157 and 1719 words: one, two and three equal
+    # chunks of a width that is not a multiple of the wavefront's 64 words
     import oracle
     g = synth.powerlaw(n, seed=synth.BASE_SEED + 5)
     R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
