@@ -212,11 +212,17 @@ class GpuBackend:
     def __init__(self):
         from . import cfpq
         self.cfpq = cfpq
+        self.streams = {}
 
     def make_stream(self, slot):
+        # one stream per slot index for the backend's lifetime: the caching
+        # allocator keeps freed blocks per stream, so servers that came and
+        # went on fresh streams would strand their cached memory
         import torch
         torch.cuda.set_device(0)
-        return torch.cuda.Stream()          # default priority
+        if slot not in self.streams:
+            self.streams[slot] = torch.cuda.Stream()   # default priority
+        return self.streams[slot]
 
     def _summ(self, res):
         it, _, _ = res.stats()
