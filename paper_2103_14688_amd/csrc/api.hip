@@ -119,9 +119,10 @@ struct cfpq_graph_s {
     DevBuf off, idx;                         // CSC per label (predecessors)
     DevBuf soff, sidx;                       // CSR per label (successors)
     std::vector<uint32_t> h_out_off, h_out;  // CSR per label (successors), host
-    // launch-chain sizes the last condensed query on this graph needed
-    // (speculation only: a chain that needs more continues, one that needs
-    // less exits its surplus launches at once)
+    // launch-chain sizes the last condensed query on this graph needed; with
+    // all three set, the next condensed query goes out in one piece with
+    // these sizes (speculation only: a chain that needs more continues on
+    // the host, one that needs less exits its surplus launches at once)
     mutable std::atomic<uint32_t> hint_trim{0}, hint_reach{0}, hint_levels{0};
 };
 
