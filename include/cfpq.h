@@ -140,6 +140,11 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                box-labelled transitions, i.e. regular queries, else
  *                CFPQ_ERR_INVALID).  AUTO picks FUSED for small graphs,
  *                CONDENSED for other regular queries, LEVELS otherwise.
+ *                A CONDENSED query on a graph that has run one before goes
+ *                out in one piece, sized by the launch chains the previous
+ *                one needed, with a single host read at the end (steps the
+ *                sizes did not cover are finished synchronously; the
+ *                answer does not depend on it).
  *   max_iters  : 0 = no limit beyond the natural bound; otherwise the query
  *                fails with CFPQ_ERR_LIMIT if the loop has not stopped after
  *                max_iters iterations.
@@ -169,8 +174,10 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                paper evaluated, Sec. 6) instead of extending it from the
  *                new edges A2 only (Sec. 3.1.1).  Same answers, iterations
  *                and per-iteration counts; for comparison.
- *   profile    : record HIP events around every launch of the levels
- *                strategy (see cfpq_result_profile); adds ~1 us per launch.
+ *   profile    : record HIP events around the closure launches of the
+ *                levels and condensed strategies and count the level
+ *                kernel's words (see cfpq_result_profile); adds ~1 us per
+ *                launch.
  *   stream     : hipStream_t for all work of the call (NULL = null stream).
  *   src_mask, dst_mask: host bitsets of ceil(n/64) words (bit v of word
  *                v / 64, LSB first; bits >= n ignored), NULL = every vertex.
@@ -290,7 +297,8 @@ cfpq_status cfpq_paths_open(cfpq_result res, uint32_t box, uint32_t u, uint32_t 
 cfpq_status cfpq_paths_next(cfpq_paths it, uint32_t *edges, uint64_t cap_edges, uint64_t *n_edges);
 void cfpq_paths_close(cfpq_paths it);
 
-/* Per-kernel profile of a query run with opts.profile (levels strategy).
+/* Per-kernel profile of a query run with opts.profile (levels and condensed
+ * strategies).
  * kind: CFPQ_KERNEL_SEED (Kronecker product with the new edges),
  * CFPQ_KERNEL_LEVEL (one frontier level of the incremental closure) or
  * CFPQ_KERNEL_WRITEBACK.  launches: number of launches of that kernel;
@@ -301,7 +309,8 @@ void cfpq_paths_close(cfpq_paths it);
  * next frontier); for a write-back 8 * ceil(n/64) * (|F_N| + 3) per row of
  * each box; for a condensed level (CFPQ_KERNEL_COND_LEVEL, one topological
  * level of the component graph) 8 bytes per word of component rows it writes
- * (answer rows in full, other rows only in their non-empty 512-word chunks)
+ * (answer rows in full, other rows only in their non-empty chunks, a row
+ * cut into ceil(ceil(n/64) / 832) equal chunks)
  * plus 8 bytes per word of predecessor rows it ORs in; CFPQ_KERNEL_COND_SCC sums the
  * component search (no byte count); CFPQ_KERNEL_NT_MFMA (matrix-core
  * nonterminal products in closure levels) reports int8 operations, 2 per
