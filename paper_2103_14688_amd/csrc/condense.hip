@@ -528,7 +528,12 @@ __device__ __forceinline__ uint64_t *comp_row(uint32_t c, uint32_t n, uint32_t P
     return R + (uint64_t)c * P;
 }
 
-constexpr uint32_t kCondPredCap = 8;     // predecessor rows listed per node; more take the whole-wave path
+// predecessor rows listed per node; more take the whole-wavefront path (a
+// compile-time tuning parameter)
+#ifndef CFPQ_COND_PRED_CAP
+#define CFPQ_COND_PRED_CAP 8
+#endif
+constexpr uint32_t kCondPredCap = CFPQ_COND_PRED_CAP;
 // lanes per node when OR-ing rows (kWave / kCondGroupLanes nodes at a time);
 // a compile-time tuning parameter
 // nodes per step of the row phase with a whole wavefront per node (their
