@@ -130,3 +130,25 @@ def test_graph_from_device_arrays():
     assert graph.info() == (g.n, len(g.labels), len(set(zip(g.src.tolist(), g.lbl.tolist(), g.dst.tolist()))))
     res = cfpq.query(graph, cfpq.Query(rsm_mod.from_regex(synth.RPQ_C2, g.labels)))
     check(res, want, g.n)
+
+
+def test_condensed_repeated_queries_with_masks_and_ranks():
+    # one graph handle, so later queries take the one-read path sized by the
+    # previous one: unmasked, masked, with ranks, again unmasked; every answer
+    # against the oracle restricted to the masks
+    g = synth.powerlaw(3000, seed=83)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
+    want = H.oracle_regex(g, synth.RPQ_C2)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    src, dst = masks(g.n, 84)
+    runs = [dict(), dict(src_mask=src), dict(src_mask=src, dst_mask=dst, keep_rank=True), dict(),
+            dict(keep_rank=True), dict(dst_mask=dst), dict()]
+    for kw in runs:
+        res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_CONDENSED, **kw)
+        check(res, restrict(want, g.n, kw.get("src_mask"), kw.get("dst_mask")), g.n)
+        if kw.get("keep_rank"):
+            pairs = res.pairs(0)
+            for u, v in pairs[:: max(1, len(pairs) // 5)].tolist():
+                path = res.extract_path(u, v)   # every word of the query has a c edge
+                assert path[0][0] == u and path[-1][2] == v
