@@ -270,6 +270,11 @@ def test_rpq_bench_size_sampled_rows(strategy):
     it, deltas, _ = res.stats()
     total = int(np.unpackbits(bm.view(np.uint8)).sum())
     assert res.count(0) == total == deltas[0] and it == 2
+    # the same query again on the same graph handle (for the condensed
+    # strategy: the one-read path the bench times) gives the same answer
+    again = cfpq.query(graph, q, strategy=strategy)
+    assert again.count(0) == total and again.hash(0) == res.hash(0)
+    assert np.array_equal(again.bitmap(0)[srcs], want)
 
 
 @pytest.mark.parametrize("n", [36865, 74000, 110000])
