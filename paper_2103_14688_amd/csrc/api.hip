@@ -978,14 +978,15 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     pg.in_off = tb.in_off; pg.in_tr = tb.in_tr; pg.out_off = tb.out_off; pg.out_tr = tb.out_tr;
     pg.src_mask = res.src_mask.as<uint64_t>();
 
-    hipEvent_t ev[4];
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     struct EvGuard {
         hipEvent_t *e;
         ~EvGuard() {
-            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+            for (int i = 0; i < 4; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
         }
     } evg{ev};
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
     const bool prof = o.profile != 0;
     res.profiled = prof;
 
@@ -1403,13 +1404,16 @@ cfpq_status run_fused_jobs(std::vector<FusedJob> &jobs, const cfpq_query_opts &o
     uint32_t *next = (uint32_t *)(base + qs.size() * sizeof(FusedQuery));
     HIP_TRY(hipMemcpyAsync(base, qs.data(), qs.size() * sizeof(FusedQuery), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(next, 0, 4, s));
-    hipEvent_t ev0, ev1;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    struct EvGuard {
+        hipEvent_t *a, *b;
+        ~EvGuard() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } evg{&ev0, &ev1};
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
-    struct EvGuard {
-        hipEvent_t a, b;
-        ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-    } evg{ev0, ev1};
     HIP_TRY(hipEventRecord(ev0, s));
     HIP_TRY(launch_fused((const FusedQuery *)base, (uint32_t)qs.size(), next, s));
     HIP_TRY(hipEventRecord(ev1, s));
