@@ -363,6 +363,26 @@ def test_condensed_repeated_queries_deep_and_shallow():
         check_box(res, want[text], g.n)
 
 
+@pytest.mark.parametrize("graph_kind", ["dag", "ring", "empty"])
+def test_condensed_repeated_degenerate_queries(graph_kind):
+    # one handle: nullable, missing-label and plain queries after each other
+    # on a graph that trimming empties (a DAG), one big cycle, or no edges
+    if graph_kind == "dag":
+        edges = [(i, "a" if i % 2 else "b", j) for i in range(200) for j in (i + 1, i + 7) if j < 200]
+    elif graph_kind == "ring":
+        edges = [(i, "a" if i % 3 else "b", (i + 1) % 300) for i in range(300)]
+    else:
+        edges = []
+    n = {"dag": 200, "ring": 300, "empty": 50}[graph_kind]
+    g = synth.make_graph(n, edges, ["a", "b"])
+    graph = cfpq.Graph.from_synth(g)
+    texts = ["a*", "eps", "(a | b)+", "zz", "a b* | b", "a*", "(a b)*", "eps", "(a | b)+"]
+    want = {t: H.oracle_regex(g, t) for t in set(texts)}
+    for text in texts:
+        res = cfpq.query(graph, cfpq.Query(rsm_mod.from_regex(text, g.labels)), strategy=cfpq.STRATEGY_CONDENSED)
+        check_box(res, want[text], g.n)
+
+
 def test_condensed_rejects_grammars():
     g = synth.chain("aabb")
     graph = cfpq.Graph.from_synth(g)
