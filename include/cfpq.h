@@ -224,6 +224,39 @@ cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm *rsms, uin
                              const cfpq_query_opts *opts, cfpq_result *results);
 
 /* ------------------------------------------------------------------------
+ * Query that allocates no device memory.  For callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It runs the same fixpoint as cfpq_query with
+ * CFPQ_STRATEGY_FUSED (one workgroup runs the whole loop) and writes box's
+ * relation to dst; every buffer of the query (RSM tables, closure rows,
+ * nonterminal matrices, frontiers, counters) lives in one static device array
+ * of CFPQ_NOALLOC_SCRATCH_BYTES, which each device the library runs on holds
+ * from the first call on it until the process ends.
+ *
+ * dst       : device pointer, row-major bitmap of n * ceil(n/64) words (see
+ *             conventions), caller-owned; dst_words its size.
+ * pairs, iterations: host pointers (may be NULL) receiving the number of
+ *             pairs of box's relation and the iterations of the loop.
+ * stream    : hipStream_t for the work (NULL = null stream); the call returns
+ *             after the stream has finished it.
+ * The array keeps the last call's contents; a call clears what it needs.
+ * Calls share the device's array: the library holds a per-device lock for
+ * the whole call, so calls from threads of one process run one at a time,
+ * while calls that overlap on one GPU from anywhere else (another process's
+ * copy of the library aside, which has its own array) would race.
+ * Errors: CFPQ_ERR_INVALID (NULL handles or dst, box out of range, RSM uses
+ *   more terminals than the graph has labels, graph on another device);
+ *   CFPQ_ERR_BUFFER if dst_words < n * ceil(n/64); CFPQ_ERR_LIMIT if
+ *   n > 2048, more than 64 boxes, or the query's working set exceeds
+ *   CFPQ_NOALLOC_SCRATCH_BYTES (message states both sizes);
+ *   CFPQ_ERR_DEVICE on a failed HIP call.
+ * ---------------------------------------------------------------------- */
+#define CFPQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+cfpq_status cfpq_query_noalloc(cfpq_graph g, cfpq_rsm r, uint32_t box, uint64_t *dst, uint64_t dst_words,
+                               uint64_t *pairs, uint32_t *iterations, void *stream);
+
+/* ------------------------------------------------------------------------
  * Result accessors.  "box" selects a nonterminal; its relation is the set
  * of (u, v) such that some path u..v spells a word the box derives
  * (Theorem 1).

@@ -30,7 +30,7 @@ EXPORTS = [
     "cfpq_query", "cfpq_query_batch", "cfpq_result_count", "cfpq_result_hash", "cfpq_result_bitmap",
     "cfpq_result_pairs", "cfpq_result_block", "cfpq_result_stats", "cfpq_result_profile", "cfpq_extract_path",
     "cfpq_result_destroy", "cfpq_last_error", "cfpq_version", "cfpq_paths_open", "cfpq_paths_next",
-    "cfpq_paths_close",
+    "cfpq_paths_close", "cfpq_query_noalloc",
 ]
 
 
@@ -86,6 +86,7 @@ def load():
         "cfpq_extract_path": [vp, u32, u32, u32, vp, u64, P(u64)],
         "cfpq_paths_open": [vp, u32, u32, u32, u32, P(vp)],
         "cfpq_paths_next": [vp, vp, u64, P(u64)],
+        "cfpq_query_noalloc": [vp, vp, u32, vp, u64, P(u64), P(u32), vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -246,6 +247,16 @@ def cfpq_query(g, r, opts=None):
     out = ctypes.c_void_p()
     _check(load().cfpq_query(g, r, ctypes.byref(opts) if opts is not None else None, ctypes.byref(out)))
     return out.value
+
+
+def cfpq_query_noalloc(g, r, box, dst, stream=None):
+    """The fused fixpoint without device allocation: box's relation into dst,
+    a torch CUDA tensor of n * ceil(n/64) int64/uint64 words (row-major
+    bitmap).  Returns (pairs, iterations)."""
+    pairs, it = ctypes.c_uint64(), ctypes.c_uint32()
+    _check(load().cfpq_query_noalloc(g, r, box, ctypes.c_void_p(dst.data_ptr()), dst.numel(), ctypes.byref(pairs),
+                                     ctypes.byref(it), stream))
+    return pairs.value, it.value
 
 
 def cfpq_query_batch(graphs, rsms, opts=None):
@@ -485,6 +496,20 @@ def query(graph, q, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_b
     o = make_opts(strategy, max_iters, keep_rank, keep_blocks, tile_words, stream, graph._alloc, profile, nt_mode,
                   sm, dm, recompute)
     return Result(cfpq_query(graph.h, q.h, o), graph, q)
+
+
+def query_noalloc(graph, q, box=0, dst=None, stream=None):
+    """cfpq_query_noalloc on the current torch stream; dst defaults to a new
+    tensor (allocated here by torch, not by the library).  Returns
+    (bitmap tensor [n, ceil(n/64)], pairs, iterations)."""
+    import torch
+    if stream is None:
+        stream = current_stream()
+    if dst is None:
+        dst = torch.empty((graph.n, (graph.n + 63) // 64), dtype=torch.int64, device="cuda")
+    b = q.rsm.box(box) if isinstance(box, str) else int(box)
+    pairs, it = cfpq_query_noalloc(graph.h, q.h, b, dst, stream)
+    return dst, pairs, it
 
 
 def query_batch(graphs, queries, strategy=STRATEGY_AUTO, max_iters=0, keep_rank=False, keep_blocks=False,

@@ -416,42 +416,59 @@ struct Tables {
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
 
-cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
+// the tables packed into one host block (16-byte aligned parts) and the
+// offset of each part in it
+struct TableImage {
     std::vector<uint8_t> host;
+    size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src;
+};
+
+void pack_tables(const Plan &p, TableImage &im) {
+    std::vector<uint8_t> &host = im.host;
+    host.clear();
     auto put = [&](const void *src, size_t bytes) {
         size_t at = (host.size() + 15) / 16 * 16;
         host.resize(at + bytes + 16);
         if (bytes) std::memcpy(host.data() + at, src, bytes);
         return at;
     };
-    size_t o_in_off = put(p.in_off.data(), p.in_off.size() * 4);
-    size_t o_in_tr = put(p.in_tr.data(), p.in_tr.size() * sizeof(InTrans));
-    size_t o_starts = put(p.starts.data(), p.starts.size() * 4);
-    size_t o_fin_off = put(p.fin_off.data(), p.fin_off.size() * 4);
-    size_t o_fin = put(p.fin.data(), p.fin.size() * 4);
-    size_t o_eps = put(p.eps_boxes.data(), p.eps_boxes.size() * 4);
-    size_t o_null = put(p.nullable.data(), p.nullable.size());
-    size_t o_used = put(p.box_used.data(), p.box_used.size());
-    size_t o_out_off = put(p.out_off.data(), p.out_off.size() * 4);
-    size_t o_out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
-    size_t o_is_start = put(p.is_start.data(), p.is_start.size() * 4);
-    size_t o_nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
-    if (!t.buf.alloc(al, host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
-    HIP_TRY(hipMemcpyAsync(t.buf.p, host.data(), host.size(), hipMemcpyHostToDevice, s));
-    uint8_t *b = t.buf.as<uint8_t>();
-    t.in_off = (uint32_t *)(b + o_in_off);
-    t.in_tr = (InTrans *)(b + o_in_tr);
-    t.starts = (uint32_t *)(b + o_starts);
-    t.fin_off = (uint32_t *)(b + o_fin_off);
-    t.fin = (uint32_t *)(b + o_fin);
-    t.eps = (uint32_t *)(b + o_eps);
-    t.nullable = b + o_null;
-    t.box_used = b + o_used;
-    t.out_off = (uint32_t *)(b + o_out_off);
-    t.out_tr = (InTrans *)(b + o_out_tr);
-    t.is_start = (uint32_t *)(b + o_is_start);
-    t.nt_src = (uint32_t *)(b + o_nt_src);
-    // the host vector dies with this frame: wait for the copy
+    im.in_off = put(p.in_off.data(), p.in_off.size() * 4);
+    im.in_tr = put(p.in_tr.data(), p.in_tr.size() * sizeof(InTrans));
+    im.starts = put(p.starts.data(), p.starts.size() * 4);
+    im.fin_off = put(p.fin_off.data(), p.fin_off.size() * 4);
+    im.fin = put(p.fin.data(), p.fin.size() * 4);
+    im.eps = put(p.eps_boxes.data(), p.eps_boxes.size() * 4);
+    im.nullable = put(p.nullable.data(), p.nullable.size());
+    im.box_used = put(p.box_used.data(), p.box_used.size());
+    im.out_off = put(p.out_off.data(), p.out_off.size() * 4);
+    im.out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
+    im.is_start = put(p.is_start.data(), p.is_start.size() * 4);
+    im.nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
+}
+
+// table pointers into a device copy of the image at b
+void bind_tables(const TableImage &im, uint8_t *b, Tables &t) {
+    t.in_off = (uint32_t *)(b + im.in_off);
+    t.in_tr = (InTrans *)(b + im.in_tr);
+    t.starts = (uint32_t *)(b + im.starts);
+    t.fin_off = (uint32_t *)(b + im.fin_off);
+    t.fin = (uint32_t *)(b + im.fin);
+    t.eps = (uint32_t *)(b + im.eps);
+    t.nullable = b + im.nullable;
+    t.box_used = b + im.box_used;
+    t.out_off = (uint32_t *)(b + im.out_off);
+    t.out_tr = (InTrans *)(b + im.out_tr);
+    t.is_start = (uint32_t *)(b + im.is_start);
+    t.nt_src = (uint32_t *)(b + im.nt_src);
+}
+
+cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
+    TableImage im;
+    pack_tables(p, im);
+    if (!t.buf.alloc(al, im.host.size(), s)) return fail(CFPQ_ERR_OOM, "device allocation failed (tables)");
+    HIP_TRY(hipMemcpyAsync(t.buf.p, im.host.data(), im.host.size(), hipMemcpyHostToDevice, s));
+    bind_tables(im, t.buf.as<uint8_t>(), t);
+    // the host image dies with this frame: wait for the copy
     HIP_TRY(hipStreamSynchronize(s));
     return CFPQ_OK;
 }
@@ -1353,6 +1370,39 @@ bool fused_ok(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     return g.n <= kFusedMaxN && r.n_boxes <= kFusedMaxBoxesHost;
 }
 
+// words of the fused kernel's work area beyond T and NT: the frontiers D, Dn,
+// dNT, three activity bitsets, dnt_act and the statistics
+uint64_t fused_work_words(const Plan &p) {
+    const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
+    const uint64_t aw = (uint64_t)p.nQ * p.Pn, bb = (uint64_t)p.nB * p.Pn;
+    return 2 * qw + bw + 3 * aw + bb + 2 + kStatsCap;
+}
+
+// the fused query's arguments with its buffers carved from work
+// (fused_work_words(p) words); rank off, no iteration limit
+void fill_fused(const Plan &p, const cfpq_graph_s &g, const Tables &tb, uint64_t *T, uint64_t *NT, uint64_t *w,
+                FusedQuery &q) {
+    const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
+    const uint64_t aw = (uint64_t)p.nQ * p.Pn, bb = (uint64_t)p.nB * p.Pn;
+    q = FusedQuery{};
+    q.n = p.n; q.P = p.P; q.Pn = p.Pn; q.n_terms = p.n_terms; q.nQ = p.nQ; q.nB = p.nB;
+    q.goff = g.off.as<uint32_t>(); q.gidx = g.idx.as<uint32_t>();
+    q.in_off = tb.in_off; q.in_tr = tb.in_tr; q.starts = tb.starts;
+    q.fin_off = tb.fin_off; q.fin = tb.fin; q.nullable = tb.nullable; q.box_used = tb.box_used;
+    q.T = T; q.NT = NT;
+    q.D = w; w += qw;
+    q.Dn = w; w += qw;
+    q.dNT = w; w += bw;
+    q.act = w; w += aw;
+    q.actn = w; w += aw;
+    q.tnz = w; w += aw;
+    q.dnt_act = w; w += bb;
+    q.stats = (unsigned long long *)w;
+    q.rank = nullptr;
+    q.max_iters = 0;
+    q.stats_cap = kStatsCap;
+}
+
 cfpq_status prepare_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o,
                           cfpq_result_s &res, FusedJob &job) {
     hipStream_t s = (hipStream_t)o.stream;
@@ -1362,32 +1412,16 @@ cfpq_status prepare_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     if (st != CFPQ_OK) return st;
     const Plan &p = job.plan;
     const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
-    const uint64_t aw = (uint64_t)p.nQ * p.Pn, bb = (uint64_t)p.nB * p.Pn;
-    const uint64_t words = 2 * qw /*D, Dn*/ + bw /*dNT*/ + 3 * aw + bb + 2 + kStatsCap;
+    const uint64_t words = fused_work_words(p);
     if (!job.T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !job.work.alloc(al, words * 8, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (fused query)");
     if (o.keep_rank) {
         if (!res.rank.alloc(al, (uint64_t)p.nB * p.n * p.n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
         HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)p.nB * p.n * p.n, s));
     }
-    uint64_t *w = job.work.as<uint64_t>();
-    FusedQuery &q = job.q;
-    q.n = p.n; q.P = p.P; q.Pn = p.Pn; q.n_terms = p.n_terms; q.nQ = p.nQ; q.nB = p.nB;
-    q.goff = g.off.as<uint32_t>(); q.gidx = g.idx.as<uint32_t>();
-    q.in_off = job.tb.in_off; q.in_tr = job.tb.in_tr; q.starts = job.tb.starts;
-    q.fin_off = job.tb.fin_off; q.fin = job.tb.fin; q.nullable = job.tb.nullable; q.box_used = job.tb.box_used;
-    q.T = job.T.as<uint64_t>(); q.NT = res.NT.as<uint64_t>();
-    q.D = w; w += qw;
-    q.Dn = w; w += qw;
-    q.dNT = w; w += bw;
-    q.act = w; w += aw;
-    q.actn = w; w += aw;
-    q.tnz = w; w += aw;
-    q.dnt_act = w; w += bb;
-    q.stats = (unsigned long long *)w;
-    q.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
-    q.max_iters = o.max_iters;
-    q.stats_cap = kStatsCap;
+    fill_fused(p, g, job.tb, job.T.as<uint64_t>(), res.NT.as<uint64_t>(), job.work.as<uint64_t>(), job.q);
+    job.q.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
+    job.q.max_iters = o.max_iters;
     job.res = &res;
     job.keep_blocks = o.keep_blocks;
     return CFPQ_OK;
@@ -1573,6 +1607,103 @@ extern "C" cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm
         return fail(CFPQ_ERR_OOM, "host allocation failed");
     }
     for (uint32_t i = 0; i < k; ++i) results[i] = res[i].release();
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// query without device allocation: the fused fixpoint with its whole working
+// set in a static device array
+// ---------------------------------------------------------------------------
+namespace noalloc {
+// One copy per device, resident from the library's first use of that device
+// until the process ends.  Host code never takes this name's address: a
+// kernel given it would fault.  It uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint64_t scratch[CFPQ_NOALLOC_SCRATCH_BYTES / 8];
+}  // namespace noalloc
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+// per device: a lock held for a whole call (calls in one process never
+// overlap on a device) and the device address of that device's array
+std::mutex g_noalloc_mu[kNoAllocDevices];
+uint64_t *g_noalloc_ptr[kNoAllocDevices];
+
+// the array's device address on device dev (current); the caller holds
+// g_noalloc_mu[dev]
+cfpq_status noalloc_scratch(int dev, uint64_t **out) {
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc::scratch));
+        if (e != hipSuccess || !p)
+            return fail(CFPQ_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = static_cast<uint64_t *>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return CFPQ_OK;
+}
+
+constexpr uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+extern "C" cfpq_status cfpq_query_noalloc(cfpq_graph g, cfpq_rsm r, uint32_t box, uint64_t *dst, uint64_t dst_words,
+                                          uint64_t *pairs, uint32_t *iterations, void *stream) {
+    cfpq_status st = check_pair(g, r);
+    if (st != CFPQ_OK) return st;
+    if (box >= r->n_boxes) return fail(CFPQ_ERR_INVALID, "box out of range");
+    if (!dst) return fail(CFPQ_ERR_INVALID, "dst is NULL");
+    const uint32_t n = g->n, Pn = (n + 63) / 64;
+    const uint64_t need = (uint64_t)n * Pn;
+    if (dst_words < need) return fail(CFPQ_ERR_BUFFER, "bitmap buffer too small: need " + std::to_string(need) + " words");
+    if (!fused_ok(*g, *r)) return fail(CFPQ_ERR_LIMIT, "cfpq_query_noalloc needs n <= 2048 and at most 64 boxes");
+    const int dev = g->device;
+    if (dev < 0 || dev >= kNoAllocDevices) return fail(CFPQ_ERR_LIMIT, "device index beyond the static table");
+    hipStream_t s = (hipStream_t)stream;
+    try {
+        const Plan p = make_plan(*g, *r);
+        TableImage im;
+        pack_tables(p, im);
+        // layout: control words (queue head, pair count), the query's
+        // arguments, the tables, T, NT, the rest of the work area
+        const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
+        const uint64_t o_args = 256, o_tab = o_args + align256(sizeof(FusedQuery));
+        const uint64_t o_T = o_tab + align256(im.host.size());
+        const uint64_t o_NT = o_T + align256(qw * 8), o_work = o_NT + align256(bw * 8);
+        const uint64_t total = o_work + fused_work_words(p) * 8;
+        if (total > CFPQ_NOALLOC_SCRATCH_BYTES)
+            return fail(CFPQ_ERR_LIMIT, "query needs " + std::to_string(total) + " bytes of working set, the static " +
+                                            "array holds " + std::to_string((uint64_t)CFPQ_NOALLOC_SCRATCH_BYTES));
+        std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+        uint64_t *base = nullptr;
+        if ((st = noalloc_scratch(dev, &base)) != CFPQ_OK) return st;
+        uint8_t *b8 = reinterpret_cast<uint8_t *>(base);
+        Tables tb;
+        bind_tables(im, b8 + o_tab, tb);
+        FusedQuery q{};
+        fill_fused(p, *g, tb, (uint64_t *)(b8 + o_T), (uint64_t *)(b8 + o_NT), (uint64_t *)(b8 + o_work), q);
+        uint32_t *next = (uint32_t *)b8;
+        unsigned long long *count = (unsigned long long *)(b8 + 8);
+        // the previous call's contents are still there: the queue head and
+        // the count start at zero; the kernel clears its own buffers
+        HIP_TRY(launch_fill(base, 2, 0, s));
+        HIP_TRY(hipMemcpyAsync(b8 + o_tab, im.host.data(), im.host.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(b8 + o_args, &q, sizeof(q), hipMemcpyHostToDevice, s));
+        HIP_TRY(launch_fused((const FusedQuery *)(b8 + o_args), 1, next, s));
+        const uint64_t *rows = q.NT + (uint64_t)box * n * p.P;
+        HIP_TRY(launch_transpose(rows, p.P, dst, Pn, n, s));
+        HIP_TRY(launch_popcount(rows, n, p.P, Pn, count, s));
+        unsigned long long stats[2] = {0, 0}, cnt = 0;
+        HIP_TRY(hipMemcpyAsync(stats, q.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&cnt, count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (stats[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop");
+        if (pairs) *pairs = cnt;
+        if (iterations) *iterations = (uint32_t)stats[0];
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
+    }
     return CFPQ_OK;
 }
 
@@ -2095,4 +2226,4 @@ extern "C" void cfpq_paths_close(cfpq_paths it) { delete it; }
 
 extern "C" const char *cfpq_last_error(void) { return g_err.c_str(); }
 
-extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.7"; }
+extern "C" const char *cfpq_version(void) { return "cfpq-gfx950 0.8"; }
