@@ -10,9 +10,12 @@ proved to reach (Theorem 1; reachability semantics in Sec. 2.1):
     R_N = {(u, v) : some path u..v spells a word derivable from N}
 
 ``cfl_reach`` evaluates it with a worklist over the grammar's normal form
-(``cfl_oracle.c``); ``rpq_rows`` evaluates a regular path query by one
-breadth-first search per source over the graph x epsilon-NFA product
-(Sec. 2.2 and 2.4: RPQ as automata intersection).
+(``cfl_oracle.c``); ``cfl_reach_rounds`` evaluates the same normal form as a
+least fixpoint of relation equations in semi-naive rounds (larger graphs);
+``rpq_rows`` evaluates a regular path query by one breadth-first search per
+source over the graph x epsilon-NFA product (Sec. 2.2 and 2.4: RPQ as
+automata intersection).  ``pairs_hash`` and ``groups_hash`` give the count
+and order-independent hash of pair sets too large to store.
 
 All arithmetic is Boolean or integer; results are exact.
 """
@@ -55,6 +58,14 @@ def _load():
         lib.oracle_cfl.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p, u32p, u32p,
                                    ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u32p, u32p,
                                    ctypes.c_uint32, u32p, u64p, u64p, u64p]
+        lib.oracle_cfl_rounds.restype = ctypes.c_int
+        lib.oracle_cfl_rounds.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p, u32p, u32p,
+                                          ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u32p, u32p,
+                                          ctypes.c_uint32, u32p, u64p, u64p, ctypes.c_int, u32p]
+        lib.oracle_pairs_hash.restype = None
+        lib.oracle_pairs_hash.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p, u64p, ctypes.c_int, u64p, u64p]
+        lib.oracle_groups_hash.restype = None
+        lib.oracle_groups_hash.argtypes = [ctypes.c_uint32, u64p, u32p, ctypes.c_int, u64p, u64p]
         lib.oracle_rpq_rows.restype = ctypes.c_int
         lib.oracle_rpq_rows.argtypes = [ctypes.c_uint32, ctypes.c_uint64, u32p, u32p, u32p,
                                         ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, u32p, u32p, u32p,
@@ -109,6 +120,59 @@ def cfl_reach(n, src, lbl, dst, label_names, grammar, nonterminals=None, bitmaps
     if rc != 0:
         raise RuntimeError(f"oracle_cfl failed ({rc})")
     return {a: (int(counts[i]), bits[i] if bitmaps else None) for i, a in enumerate(want)}
+
+
+def cfl_reach_rounds(n, src, lbl, dst, label_names, grammar, nonterminals=None, threads=1, bitmaps=True):
+    """The relation of ``cfl_reach`` by semi-naive rounds over n x n bitsets
+    (``oracle_cfl_rounds``): needs 3 n^2/8 bytes per normal-form nonterminal,
+    but no per-fact joins, so it reaches larger graphs.  Returns
+    ({name: (count, bitmap or None)}, rounds)."""
+    lib = _load()
+    label_ids = {name: i for i, name in enumerate(label_names)}
+    n_nt, rules, names = lang.grammar_normal_form(grammar, label_ids)
+    want = list(names) if nonterminals is None else list(nonterminals)
+    out_nt = _u32([names.index(a) for a in want])
+    src, lbl, dst = _u32(src), _u32(lbl), _u32(dst)
+    kind = _u32([r[0] for r in rules])
+    lhs = _u32([r[1] for r in rules])
+    x = _u32([r[2] for r in rules])
+    y = _u32([r[3] for r in rules])
+    w = words(n)
+    bits = np.zeros((len(want), n, w), dtype=np.uint64) if bitmaps else None
+    counts = np.zeros(len(want), dtype=np.uint64)
+    rounds = np.zeros(1, dtype=np.uint32)
+    rc = lib.oracle_cfl_rounds(n, len(src), _p32(src), _p32(lbl), _p32(dst), n_nt, len(rules),
+                               _p32(kind), _p32(lhs), _p32(x), _p32(y), len(want), _p32(out_nt),
+                               _p64(bits) if bitmaps else None, _p64(counts), int(threads), _p32(rounds))
+    if rc != 0:
+        raise RuntimeError(f"oracle_cfl_rounds failed ({rc})")
+    return {a: (int(counts[i]), bits[i] if bitmaps else None) for i, a in enumerate(want)}, int(rounds[0])
+
+
+def pairs_hash(bm, n, row_ids=None, threads=1):
+    """(count, hash) of the pairs of bitmap rows bm [rows, ceil(n/64)]: row i
+    is vertex row_ids[i] (default i); hash = sum of splitmix64((u << 32) | v)
+    mod 2^64 (SplitMix64 of Steele, Lea and Flood, 2014)."""
+    lib = _load()
+    bm = np.ascontiguousarray(bm, dtype=np.uint64)
+    ids = None if row_ids is None else _u32(row_ids)
+    c = np.zeros(1, dtype=np.uint64)
+    h = np.zeros(1, dtype=np.uint64)
+    lib.oracle_pairs_hash(n, bm.shape[0], _p32(ids) if ids is not None else None, _p64(bm), int(threads),
+                          _p64(c), _p64(h))
+    return int(c[0]), int(h[0])
+
+
+def groups_hash(groups, threads=1):
+    """(count, hash) of the union of G x G over disjoint vertex groups."""
+    lib = _load()
+    off = np.zeros(len(groups) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(g) for g in groups])
+    members = _u32(np.concatenate([np.asarray(g, dtype=np.uint32) for g in groups]) if groups else [])
+    c = np.zeros(1, dtype=np.uint64)
+    h = np.zeros(1, dtype=np.uint64)
+    lib.oracle_groups_hash(len(groups), _p64(off), _p32(members), int(threads), _p64(c), _p64(h))
+    return int(c[0]), int(h[0])
 
 
 def rpq_rows(n, src, lbl, dst, label_names, regex, sources, threads=1, return_visits=False):

@@ -29,6 +29,16 @@
  *    is in the source's row iff some product node (v, q) with q final is
  *    reachable from (source, q0).  Sources are independent, so they may run
  *    on several threads.
+ *
+ * 3. oracle_cfl_rounds: the relation of 1. as the least fixpoint of the
+ *    normal-form grammar read as equations over relations, evaluated in
+ *    semi-naive rounds on n x n bitsets (for graphs too large for the
+ *    worklist's per-fact joins); see its own comment.
+ *
+ * 4. oracle_pairs_hash, oracle_groups_hash: pair count and the
+ *    order-independent hash (sum of SplitMix64 over (u << 32) | v) of a pair
+ *    set given as bitmap rows or as a union of squares G x G, for comparing
+ *    relations too large to keep as bitmaps.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -371,4 +381,240 @@ int oracle_rpq_rows(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t 
     if (visits) *visits = total_visits;
     free(off); free(adj); free(toff); free(tord);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* semi-naive rounds over relation bitsets                             */
+/* ------------------------------------------------------------------ */
+/*
+ * 3. oracle_cfl_rounds: the same relation as oracle_cfl (same normal form,
+ *    same arguments), computed as the least fixpoint of the grammar read as
+ *    equations over binary relations on the vertices:
+ *        R_A  contains  the diagonal          for A -> eps
+ *             contains  the edges of label t  for A -> t
+ *             contains  R_B                   for A -> B
+ *             contains  R_B ; R_C             for A -> B C
+ *    (";" is relational composition: (u, w) with some v, (u,v) in R_B and
+ *    (v,w) in R_C).  Round 0 holds the eps and terminal facts.  Round k+1
+ *    adds what the unit and binary rules derive from facts of which at least
+ *    one is new in round k (semi-naive evaluation: a pair of two older facts
+ *    was already composed in an earlier round); it stops when a round adds
+ *    nothing.  Every relation is an n x n bitset (row u: the v with (u, v));
+ *    so memory is 3 n^2/8 bytes per nonterminal (relation, last round's new
+ *    facts, this round's new facts).  Rows of one composition are computed in
+ *    parallel on `threads` threads.  rounds (optional) receives the number of
+ *    rounds, the last (empty) one included.
+ * Returns 0, -1 on bad input, -2 when memory runs out.
+ */
+#define NOT_LISTED 0xFFFFFFFFu
+
+typedef struct {
+    uint64_t *rel, *cur, *nxt;   /* n * W words each */
+    uint64_t rel_count, cur_count;
+} relset;
+
+static uint64_t bits_count(const uint64_t *b, uint64_t words) {
+    uint64_t c = 0;
+    for (uint64_t i = 0; i < words; i++) c += (uint64_t)__builtin_popcountll(b[i]);
+    return c;
+}
+
+/* out |= X ; Y  (rows u of out: OR of rows Y[v] over v in X[u]).  When Y
+ * holds few pairs its rows are walked as lists (built here), otherwise they
+ * are OR-ed word by word; X[u] is first restricted to the v whose Y row is
+ * non-empty. */
+static int compose_into(uint64_t *out, const uint64_t *X, const uint64_t *Y, uint64_t y_count, uint32_t n,
+                        uint64_t W, int threads) {
+    uint64_t *ynz = (uint64_t *)calloc(W ? W : 1, sizeof(uint64_t));
+    if (!ynz) return -2;
+    for (uint32_t v = 0; v < n; v++) {
+        const uint64_t *row = Y + (uint64_t)v * W;
+        for (uint64_t k = 0; k < W; k++)
+            if (row[k]) { ynz[v >> 6] |= 1ull << (v & 63); break; }
+    }
+    /* lists when the average Y row has fewer than W/8 pairs */
+    int lists = y_count * 8 < (uint64_t)n * W;
+    uint64_t *yoff = NULL;
+    uint32_t *ycol = NULL;
+    if (lists) {
+        yoff = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
+        ycol = (uint32_t *)malloc((y_count ? y_count : 1) * sizeof(uint32_t));
+        if (!yoff || !ycol) { free(yoff); free(ycol); free(ynz); return -2; }
+        uint64_t at = 0;
+        for (uint32_t v = 0; v < n; v++) {
+            yoff[v] = at;
+            const uint64_t *row = Y + (uint64_t)v * W;
+            for (uint64_t k = 0; k < W; k++)
+                for (uint64_t b = row[k]; b; b &= b - 1) ycol[at++] = (uint32_t)(k * 64 + __builtin_ctzll(b));
+        }
+        yoff[n] = at;
+    }
+#pragma omp parallel for num_threads(threads) schedule(dynamic, 64)
+    for (uint32_t u = 0; u < n; u++) {
+        const uint64_t *xr = X + (uint64_t)u * W;
+        uint64_t *orow = out + (uint64_t)u * W;
+        for (uint64_t k = 0; k < W; k++) {
+            for (uint64_t b = xr[k] & ynz[k]; b; b &= b - 1) {
+                uint32_t v = (uint32_t)(k * 64 + __builtin_ctzll(b));
+                if (lists) {
+                    for (uint64_t e = yoff[v]; e < yoff[v + 1]; e++) {
+                        uint32_t w = ycol[e];
+                        orow[w >> 6] |= 1ull << (w & 63);
+                    }
+                } else {
+                    const uint64_t *yr = Y + (uint64_t)v * W;
+                    for (uint64_t j = 0; j < W; j++) orow[j] |= yr[j];
+                }
+            }
+        }
+    }
+    free(yoff); free(ycol); free(ynz);
+    return 0;
+}
+
+int oracle_cfl_rounds(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t *lbl, const uint32_t *dst,
+                      uint32_t n_nt, uint32_t n_rules, const uint32_t *kind, const uint32_t *lhs,
+                      const uint32_t *x, const uint32_t *y,
+                      uint32_t n_out, const uint32_t *out_nt, uint64_t *out_bits, uint64_t *out_count,
+                      int threads, uint32_t *rounds)
+{
+    for (uint32_t r = 0; r < n_rules; r++) {
+        if (lhs[r] >= n_nt) return -1;
+        if (kind[r] == R_UNIT && x[r] >= n_nt) return -1;
+        if (kind[r] == R_BIN && (x[r] >= n_nt || y[r] >= n_nt)) return -1;
+        if (kind[r] > R_BIN) return -1;
+    }
+    for (uint64_t i = 0; i < m; i++) if (src[i] >= n || dst[i] >= n) return -1;
+    for (uint32_t k = 0; k < n_out; k++) if (out_nt[k] >= n_nt) return -1;
+    if (threads < 1) threads = 1;
+
+    const uint64_t W = (n + 63) / 64, words = (uint64_t)n * W;
+    relset *R = (relset *)calloc(n_nt ? n_nt : 1, sizeof(relset));
+    if (!R) return -2;
+    int rc = 0;
+    for (uint32_t a = 0; a < n_nt && !rc; a++) {
+        R[a].rel = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
+        R[a].cur = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
+        R[a].nxt = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
+        if (!R[a].rel || !R[a].cur || !R[a].nxt) rc = -2;
+    }
+    /* round 0: eps and terminal facts are all new */
+    for (uint32_t r = 0; r < n_rules && !rc; r++) {
+        uint64_t *c = R[lhs[r]].cur;
+        if (kind[r] == R_EPS)
+            for (uint32_t u = 0; u < n; u++) c[(uint64_t)u * W + (u >> 6)] |= 1ull << (u & 63);
+        if (kind[r] == R_TERM)
+            for (uint64_t i = 0; i < m; i++)
+                if (lbl[i] == x[r]) c[(uint64_t)src[i] * W + (dst[i] >> 6)] |= 1ull << (dst[i] & 63);
+    }
+    for (uint32_t a = 0; a < n_nt && !rc; a++) {
+        memcpy(R[a].rel, R[a].cur, words * sizeof(uint64_t));
+        R[a].cur_count = R[a].rel_count = bits_count(R[a].cur, words);
+    }
+    uint32_t nr = 1;
+    for (;;) {
+        if (rc) break;
+        int any_new = 0;
+        for (uint32_t a = 0; a < n_nt; a++) any_new |= R[a].cur_count != 0;
+        if (!any_new) break;
+        nr++;
+        for (uint32_t a = 0; a < n_nt; a++) memset(R[a].nxt, 0, words * sizeof(uint64_t));
+        for (uint32_t r = 0; r < n_rules && !rc; r++) {
+            relset *A = &R[lhs[r]];
+            if (kind[r] == R_UNIT) {
+                const relset *B = &R[x[r]];
+                if (!B->cur_count) continue;
+                for (uint64_t i = 0; i < words; i++) A->nxt[i] |= B->cur[i];
+            } else if (kind[r] == R_BIN) {
+                const relset *B = &R[x[r]], *C = &R[y[r]];
+                /* new ; all  and  all ; new */
+                if (B->cur_count && C->rel_count) rc = compose_into(A->nxt, B->cur, C->rel, C->rel_count, n, W, threads);
+                if (!rc && B->rel_count && C->cur_count)
+                    rc = compose_into(A->nxt, B->rel, C->cur, C->cur_count, n, W, threads);
+            }
+        }
+        for (uint32_t a = 0; a < n_nt && !rc; a++) {
+            relset *A = &R[a];
+            uint64_t c = 0;
+            for (uint64_t i = 0; i < words; i++) {
+                uint64_t nw = A->nxt[i] & ~A->rel[i];
+                A->nxt[i] = nw;
+                A->rel[i] |= nw;
+                c += (uint64_t)__builtin_popcountll(nw);
+            }
+            uint64_t *t = A->cur; A->cur = A->nxt; A->nxt = t;
+            A->cur_count = c;
+            A->rel_count += c;
+        }
+    }
+    if (!rc) {
+        for (uint32_t o = 0; o < n_out; o++) {
+            const relset *A = &R[out_nt[o]];
+            if (out_bits) memcpy(out_bits + (uint64_t)o * words, A->rel, words * sizeof(uint64_t));
+            if (out_count) out_count[o] = A->rel_count;
+        }
+        if (rounds) *rounds = nr;
+    }
+    for (uint32_t a = 0; a < n_nt; a++) { free(R[a].rel); free(R[a].cur); free(R[a].nxt); }
+    free(R);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* count and order-independent hash of a pair set                      */
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood 2014): the first output of the generator
+ * seeded with z: z + golden gamma, then the two xor-shift-multiply steps
+ * and a final xor-shift, as published. */
+static uint64_t sm64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+/* rows of a row-major bitmap: row i is vertex row_ids[i] (or i if row_ids is
+ * NULL); adds to *count the pairs and to *hash the sum of
+ * splitmix64((u << 32) | v) over them (mod 2^64) */
+void oracle_pairs_hash(uint32_t n, uint64_t n_rows, const uint32_t *row_ids, const uint64_t *bits, int threads,
+                       uint64_t *count, uint64_t *hash)
+{
+    const uint64_t W = (n + 63) / 64;
+    uint64_t c = 0, h = 0;
+    if (threads < 1) threads = 1;
+#pragma omp parallel for num_threads(threads) reduction(+ : c, h) schedule(static)
+    for (uint64_t i = 0; i < n_rows; i++) {
+        uint64_t u = row_ids ? row_ids[i] : i;
+        const uint64_t *row = bits + i * W;
+        for (uint64_t k = 0; k < W; k++)
+            for (uint64_t b = row[k]; b; b &= b - 1) {
+                uint64_t v = k * 64 + (uint64_t)__builtin_ctzll(b);
+                c++;
+                h += sm64((u << 32) | v);
+            }
+    }
+    *count += c;
+    *hash += h;
+}
+
+/* pairs of a union of full squares G x G over disjoint vertex groups: group g
+ * is members[off[g] .. off[g+1]); count and hash as above */
+void oracle_groups_hash(uint32_t n_groups, const uint64_t *off, const uint32_t *members, int threads,
+                        uint64_t *count, uint64_t *hash)
+{
+    uint64_t c = 0, h = 0;
+    if (threads < 1) threads = 1;
+    for (uint32_t g = 0; g < n_groups; g++) {
+        int64_t lo = (int64_t)off[g], hi = (int64_t)off[g + 1];
+#pragma omp parallel for num_threads(threads) reduction(+ : c, h) schedule(dynamic, 16)
+        for (int64_t i = lo; i < hi; i++) {
+            uint64_t u = members[i];
+            for (int64_t j = lo; j < hi; j++) {
+                h += sm64((u << 32) | (uint64_t)members[j]);
+                c++;
+            }
+        }
+    }
+    *count += c;
+    *hash += h;
 }
