@@ -332,3 +332,22 @@ def paper_example_rsm(labels=("a", "b")):
     u32 = lambda x: np.asarray(x, dtype=np.uint32)
     return RSM(4, nt, ["S"], u32([0]), u32([0, 0, 0, 0]), np.asarray([0, 0, 0, 1], dtype=np.uint8),
                u32([0, 1, 2, 1]), u32([a, nt + 0, b, b]), u32([1, 2, 3, 3]), 0)
+
+
+def from_automaton(n_states, transitions, finals, labels, start=0, box_name="S"):
+    """One-box RSM from an explicit automaton (a regular query given state by
+    state): transitions are (state, label name, state) triples, finals a set
+    of states; any epsilon-free automaton serves (Sec. 2.2), deterministic or
+    not.  Labels absent from the graph's list never match and are dropped."""
+    label_id = {x: i for i, x in enumerate(labels)}
+    if not 0 <= start < n_states:
+        raise ValueError("start state out of range")
+    order = [start] + [q for q in range(n_states) if q != start]   # the box starts at state 0
+    ren = {q: i for i, q in enumerate(order)}
+    kept = [(ren[a], label_id[x], ren[b]) for a, x, b in transitions if x in label_id]
+    u32 = lambda a: np.asarray(a, dtype=np.uint32)
+    final = np.zeros(n_states, dtype=np.uint8)
+    for q in finals:
+        final[ren[q]] = 1
+    return RSM(n_states, len(labels), [box_name], u32([0]), u32([0] * n_states), final,
+               u32([t[0] for t in kept]), u32([t[1] for t in kept]), u32([t[2] for t in kept]), 0)

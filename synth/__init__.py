@@ -305,3 +305,10 @@ def serving_mix(n_graphs=64, n_queries=10000, n_range=(1000, 200000), mean_deg=3
 
 def serving_graph(n, seed, labels, mean_deg=3.0):
     return powerlaw(n, labels=tuple(labels), mean_deg=mean_deg, seed=seed)
+
+
+# (a|b)* c d* as a four-state automaton (a deterministic automaton that is
+# not minimal: the states after c and after d accept the same words):
+# 0 -a,b-> 1, 1 -a,b-> 1, 0 -c-> 2, 1 -c-> 2, 2 -d-> 3, 3 -d-> 3, final {2, 3}
+RPQ_C2_FOUR_STATE = (4, [(0, "a", 1), (0, "b", 1), (1, "a", 1), (1, "b", 1), (0, "c", 2), (1, "c", 2),
+                         (2, "d", 3), (3, "d", 3)], {2, 3})
