@@ -331,28 +331,40 @@ cfpq_status cfpq_paths_next(cfpq_paths it, uint32_t *edges, uint64_t cap_edges, 
 void cfpq_paths_close(cfpq_paths it);
 
 /* Per-kernel profile of a query run with opts.profile (levels and condensed
- * strategies).
- * kind: CFPQ_KERNEL_SEED (Kronecker product with the new edges),
- * CFPQ_KERNEL_LEVEL (one frontier level of the incremental closure) or
- * CFPQ_KERNEL_WRITEBACK.  launches: number of launches of that kernel;
- * ms: their summed device time (HIP events on the query stream, between
- * consecutive launches); bytes: the algorithmic bytes they had to move --
- * for a level launch 8 * tile_words * (R_in + 3 * R_out), R_in the frontier
- * rows read and R_out the target rows fed by them (read T, write T and the
- * next frontier); for a write-back 8 * ceil(n/64) * (|F_N| + 3) per row of
- * each box; for a condensed level (CFPQ_KERNEL_COND_LEVEL, one topological
- * level of the component graph) 8 bytes per word of component rows it writes
- * (answer rows in full, other rows only in their non-empty chunks, a row
- * cut into ceil(ceil(n/64) / 832) equal chunks)
- * plus 8 bytes per word of predecessor rows it ORs in; CFPQ_KERNEL_COND_SCC sums the
- * component search (no byte count); CFPQ_KERNEL_NT_MFMA (matrix-core
- * nonterminal products in closure levels) reports int8 operations, 2 per
- * multiply-accumulate (65536 per v_mfma_i32_32x32x32_i8), in *bytes;
- * CFPQ_KERNEL_NT_SPARSE sums the sparse nonterminal products of closure
- * levels (ELL build + LDS-accumulator product; no byte count).
+ * strategies).  Each kind is one kernel; every launch of it is bracketed by
+ * HIP events of its own on the query stream.
+ * launches: number of launches of that kernel; ms: their summed device time;
+ * bytes: the bytes of the words the kernel's algorithm reads and writes:
+ *   CFPQ_KERNEL_SEED: the Kronecker product with the new edges (the gather
+ *     over seeds; no byte count);
+ *   CFPQ_KERNEL_LEVEL: one frontier level of the incremental closure,
+ *     8 * tile_words * (R_in + 3 * R_out), R_in the frontier rows read and
+ *     R_out the target rows fed by them (read T, write T and the next
+ *     frontier);
+ *   CFPQ_KERNEL_WRITEBACK: 8 * ceil(n/64) * (|F_N| + 3) per row of box N it
+ *     visits (rows whose final-state closure rows changed in the iteration);
+ *   CFPQ_KERNEL_COND_LEVEL: one topological level of the component graph,
+ *     8 bytes per word of component rows it writes (answer rows in full,
+ *     other rows only in their non-empty chunks, a row cut into
+ *     ceil(ceil(n/64) / 832) equal chunks) plus 8 bytes per word of
+ *     predecessor rows it ORs in;
+ *   CFPQ_KERNEL_COND_SCC: the component search (no byte count);
+ *   CFPQ_KERNEL_NT_MFMA: matrix-core nonterminal products in closure levels;
+ *     *bytes receives int8 operations, 2 per multiply-accumulate (65536 per
+ *     v_mfma_i32_32x32x32_i8);
+ *   CFPQ_KERNEL_NT_SPARSE: the sparse nonterminal products (seed and closure
+ *     levels): 8 bytes per selector and source-activity word read, 4 per ELL
+ *     count and entry read, 8 * tile_words per dense source row ORed and per
+ *     product row written;
+ *   CFPQ_KERNEL_ELL: the ELL lists the sparse products read (no byte count);
+ *   CFPQ_KERNEL_NT_DENSE: the dense part of the nonterminal products (source
+ *     rows with more than 32 bits in the tile), blocked through LDS: 8 bytes
+ *     per selector word read, per source word staged, and 16 per product
+ *     word updated.
  * CFPQ_ERR_INVALID if the query was not profiled. */
 enum { CFPQ_KERNEL_SEED = 0, CFPQ_KERNEL_LEVEL = 1, CFPQ_KERNEL_WRITEBACK = 2, CFPQ_KERNEL_COND_LEVEL = 3,
-       CFPQ_KERNEL_COND_SCC = 4, CFPQ_KERNEL_NT_MFMA = 5, CFPQ_KERNEL_NT_SPARSE = 6 };
+       CFPQ_KERNEL_COND_SCC = 4, CFPQ_KERNEL_NT_MFMA = 5, CFPQ_KERNEL_NT_SPARSE = 6, CFPQ_KERNEL_ELL = 7,
+       CFPQ_KERNEL_NT_DENSE = 8 };
 cfpq_status cfpq_result_profile(cfpq_result res, uint32_t kind, uint64_t *launches, double *ms,
                                 uint64_t *bytes);
 

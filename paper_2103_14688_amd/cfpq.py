@@ -317,8 +317,8 @@ def cfpq_result_stats(res, cap=4096):
     return it.value, d[: min(it.value, cap)].tolist(), ms.value
 
 
-KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK, KERNEL_COND_LEVEL, KERNEL_COND_SCC, KERNEL_NT_MFMA, KERNEL_NT_SPARSE = \
-    0, 1, 2, 3, 4, 5, 6
+KERNEL_SEED, KERNEL_LEVEL, KERNEL_WRITEBACK, KERNEL_COND_LEVEL, KERNEL_COND_SCC, KERNEL_NT_MFMA, KERNEL_NT_SPARSE, \
+    KERNEL_ELL, KERNEL_NT_DENSE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 
 def cfpq_result_profile(res, kind):

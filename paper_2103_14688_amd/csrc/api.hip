@@ -152,7 +152,7 @@ struct cfpq_result_s {
     struct Prof {
         uint64_t launches = 0, bytes = 0;
         double ms = 0.0;
-    } prof[7];
+    } prof[9];
     bool profiled = false;
 };
 
@@ -353,6 +353,7 @@ struct Plan {
     std::vector<uint8_t> nullable, box_used;
     std::vector<uint32_t> is_start;      // per state: initial state of its box
     std::vector<uint32_t> nt_src;        // source states of box-labelled transitions
+    std::vector<uint32_t> nt_dst;        // target states of box-labelled transitions
 };
 
 Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
@@ -377,12 +378,18 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     for (size_t i = 0; i < r.t_src.size(); ++i) p.out_tr[ofill[r.t_src[i]]++] = InTrans{r.t_dst[i], r.t_sym[i]};
     for (size_t i = 0; i < r.t_sym.size(); ++i) p.has_calls |= r.t_sym[i] >= r.n_terms;
     {
-        std::vector<uint8_t> seen(p.nQ, 0);
-        for (size_t i = 0; i < r.t_sym.size(); ++i)
-            if (r.t_sym[i] >= r.n_terms && !seen[r.t_src[i]]) {
+        std::vector<uint8_t> seen(p.nQ, 0), seen_dst(p.nQ, 0);
+        for (size_t i = 0; i < r.t_sym.size(); ++i) {
+            if (r.t_sym[i] < r.n_terms) continue;
+            if (!seen[r.t_src[i]]) {
                 seen[r.t_src[i]] = 1;
                 p.nt_src.push_back(r.t_src[i]);
             }
+            if (!seen_dst[r.t_dst[i]]) {
+                seen_dst[r.t_dst[i]] = 1;
+                p.nt_dst.push_back(r.t_dst[i]);
+            }
+        }
     }
     p.starts = r.box_start;
     p.is_start.assign(p.nQ, 0);
@@ -411,7 +418,7 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
 struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
-             *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr;
+             *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr, *nt_dst = nullptr;
     InTrans *in_tr = nullptr, *out_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
@@ -420,7 +427,7 @@ struct Tables {
 // offset of each part in it
 struct TableImage {
     std::vector<uint8_t> host;
-    size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src;
+    size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src, nt_dst;
 };
 
 void pack_tables(const Plan &p, TableImage &im) {
@@ -444,6 +451,7 @@ void pack_tables(const Plan &p, TableImage &im) {
     im.out_tr = put(p.out_tr.data(), p.out_tr.size() * sizeof(InTrans));
     im.is_start = put(p.is_start.data(), p.is_start.size() * 4);
     im.nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
+    im.nt_dst = put(p.nt_dst.data(), p.nt_dst.size() * 4);
 }
 
 // table pointers into a device copy of the image at b
@@ -460,6 +468,7 @@ void bind_tables(const TableImage &im, uint8_t *b, Tables &t) {
     t.out_tr = (InTrans *)(b + im.out_tr);
     t.is_start = (uint32_t *)(b + im.is_start);
     t.nt_src = (uint32_t *)(b + im.nt_src);
+    t.nt_dst = (uint32_t *)(b + im.nt_dst);
 }
 
 cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
@@ -579,7 +588,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
             const double fixed = 8.0 * ((double)qw + 2.0 * (double)bw) + 4.0 * nQ * (double)n * (kEll + 1) +
-                                 8.0 * nB * (double)n * ((Pn + 63) / 64) + (o.keep_rank ? (double)nB * n * n : 0.0) +
+                                 16.0 * nB * (double)n * ((Pn + 63) / 64) + (o.keep_rank ? (double)nB * n * n : 0.0) +
                                  (256.0 * (1 << 20));
             const double per_word = 8.0 * 3.0 * nQ * (double)n;
             const double room = 0.92 * (double)free_b - fixed;
@@ -594,25 +603,48 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     const uint64_t fw = (uint64_t)nQ * n * G;
     const uint64_t aw = (uint64_t)nQ * Pn;
     const uint64_t ring_words = (uint64_t)kRingSlots * kSlotWords;
+    // row summaries (selector rows) and coarse frontier activity: one bit per
+    // word of a row, sum_pitch words per row; a frontier's coarse activity
+    // array follows its row bitset, Pbs = sum_pitch + 1 words per state (the
+    // last one flags "any active row")
+    const uint32_t sum_pitch = (Pn + kWave - 1) / kWave;
+    const uint32_t Pbs = sum_pitch + 1;
+    const uint64_t ab = (uint64_t)nQ * Pbs, aset = aw + ab;
 
-    DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr, ell;
+    DevBuf T, dNT, D0, D1, acts, tnz, dnt_act, ctr, ell, chg_buf, nsum, dense_buf;
     // sparse nonterminal product in the seed: ELL lists of the source rows and
     // an LDS row accumulator per wavefront (tiles up to kSparseMaxWords words)
     const bool sparse_nt = !p.nt_src.empty() && G <= kSparseMaxWords && o.nt_mode != CFPQ_NT_ROWS;
     if (sparse_nt && !ell.alloc(al, (uint64_t)nQ * n * (kEll + 1) * 4, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (sparse product index)");
+    // source rows with more than kEll bits go through the LDS-blocked dense
+    // product: their bitset [nQ][Pn] and its coarse array [nQ][Pbs]
+    const uint64_t dense_words = (uint64_t)nQ * Pn + (uint64_t)nQ * ((Pn + kWave - 1) / kWave + 1);
+    if (sparse_nt && !dense_buf.alloc(al, dense_words * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (dense rows)");
     if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) || !dNT.alloc(al, bw * 8, s) ||
-        !D0.alloc(al, fw * 8, s) || !D1.alloc(al, fw * 8, s) || !acts.alloc(al, 3 * aw * 8, s) ||
-        !tnz.alloc(al, aw * 8, s) || !dnt_act.alloc(al, (uint64_t)nB * Pn * 8, s) ||
-        !ctr.alloc(al, ring_words * 8, s))
+        !D0.alloc(al, fw * 8, s) || !D1.alloc(al, fw * 8, s) || !acts.alloc(al, 3 * aset * 8, s) ||
+        !tnz.alloc(al, aw * 8, s) || !dnt_act.alloc(al, 2ull * nB * Pn * 8, s) ||
+        !ctr.alloc(al, ring_words * 8, s) || !chg_buf.alloc(al, aw * 8, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (query state)");
+    // summary of the nonterminal matrices' rows (selectors of the closure
+    // levels), kept up to date for the rows each write-back changes
+    const bool use_nsum = p.has_calls;
+    if (use_nsum && !nsum.alloc(al, (uint64_t)nB * n * sum_pitch * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (selector summary)");
     if (o.keep_rank) {
         if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
         HIP_TRY(hipMemsetAsync(res.rank.p, 0xFF, (uint64_t)nB * n * n, s));  // 0xFF = absent
     }
     uint64_t *d_T = T.as<uint64_t>(), *d_NT = res.NT.as<uint64_t>(), *d_dNT = dNT.as<uint64_t>();
     uint64_t *Dbuf[2] = {D0.as<uint64_t>(), D1.as<uint64_t>()};
-    uint64_t *act[3] = {acts.as<uint64_t>(), acts.as<uint64_t>() + aw, acts.as<uint64_t>() + 2 * aw};
+    uint64_t *act[3] = {acts.as<uint64_t>(), acts.as<uint64_t>() + aset, acts.as<uint64_t>() + 2 * aset};
+    uint64_t *blk[3] = {act[0] + aw, act[1] + aw, act[2] + aw};
+    // new-edge activity of dNT: dact[cur] belongs to the current dNT (read by
+    // the next seed), the other one is written by the next write-back
+    uint64_t *dact[2] = {dnt_act.as<uint64_t>(), dnt_act.as<uint64_t>() + (uint64_t)nB * Pn};
+    uint32_t cur = 0;
+    uint64_t *d_chg = chg_buf.as<uint64_t>();
     unsigned long long *d_ctr = ctr.as<unsigned long long>();
 
     // events: [0] start, [1] end; profiling pool after that
@@ -647,27 +679,51 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         if (hipEventElapsedTime(&ms, ev[2 + j], ev[3 + j]) != hipSuccess) return 0.0;
         return ms;
     };
-    // two marks per level launch: before its matrix-core products and before
-    // its gather (both recorded always); the gather ends at the next mark
-    auto prof_mark2 = [&](uint32_t j, int which) -> cfpq_status {
+    // three marks per closure launch j (the seed, or one level): before its
+    // ELL build, before its nonterminal product (sparse or matrix cores) and
+    // before its gather; the gather ends at mark (j + 1, 0).  Every kernel is
+    // bracketed by marks of its own, so a kind's time is its kernels' time.
+    auto prof_mark3 = [&](uint32_t j, int which) -> cfpq_status {
         if (!prof) return CFPQ_OK;
-        hipEvent_t e = event(2 + 2 * j + (uint32_t)which);
+        hipEvent_t e = event(2 + 4 * j + (uint32_t)which);
         if (!e) return fail(CFPQ_ERR_DEVICE, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(e, s));
         return CFPQ_OK;
     };
+    // marks per group: 0 before the ELL build, 1 before the sparse (or
+    // matrix-core) product, 3 before the dense product, 2 before the gather
+    auto ev3 = [](uint32_t j, int which) -> size_t { return 2 + 4 * (size_t)j + (size_t)which; };
     auto prof_span = [&](size_t i0, size_t i1) -> double {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, ev[i0], ev[i1]) != hipSuccess) return 0.0;
         return ms;
     };
-    DevBuf mops;   // matrix-core instructions issued (profiling)
-    unsigned long long *mfma_ops = nullptr;
-    if (prof && p.has_calls) {
-        if (!mops.alloc(al, 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (profile counter)");
+    // profiling counters: matrix-core instructions issued, bytes of the
+    // sparse products, write-back rows visited per box
+    DevBuf mops;
+    unsigned long long *mfma_ops = nullptr, *sp_bytes = nullptr, *wb_rows = nullptr, *dn_bytes = nullptr;
+    if (prof) {
+        if (!mops.alloc(al, (3 + (uint64_t)nB) * 8, s))
+            return fail(CFPQ_ERR_OOM, "device allocation failed (profile counters)");
         mfma_ops = mops.as<unsigned long long>();
-        HIP_TRY(launch_fill((uint64_t *)mfma_ops, 1, 0, s));
+        sp_bytes = mfma_ops + 1;
+        dn_bytes = mfma_ops + 2;
+        wb_rows = mfma_ops + 3;
+        HIP_TRY(launch_fill((uint64_t *)mfma_ops, 3 + (uint64_t)nB, 0, s));
     }
+    uint64_t *d_dns = dense_buf.as<uint64_t>(), *d_dblk = d_dns ? d_dns + (uint64_t)nQ * Pn : nullptr;
+    DenseArgs dargs{};
+    dargs.dns = d_dns; dargs.dblk = d_dblk; dargs.nt_dst = tb.nt_dst; dargs.n_nt_dst = (uint32_t)p.nt_dst.size();
+    dargs.ell_idx = sparse_nt ? ell.as<uint32_t>() + (uint64_t)nQ * n : nullptr;
+    // the dense product: ELL build marks dense rows, the sparse product leaves
+    // them, the dense product ORs them in; a.bytes_ctr is the sparse one's
+    auto dense_product = [&](GatherArgs &ga, uint64_t *extra, const uint64_t *extra_act) -> cfpq_status {
+        dargs.extra = extra; dargs.extra_act = extra_act;
+        GatherArgs gd = ga;
+        gd.bytes_ctr = dn_bytes;
+        HIP_TRY(launch_nt_dense(gd, dargs, s));
+        return CFPQ_OK;
+    };
     DevBuf Dx, xact;   // matrix-core product rows and their activity, allocated on first use
 
     HIP_TRY(hipEventRecord(ev[0], s));
@@ -675,21 +731,24 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     HIP_TRY(launch_fill(d_NT, bw, 0, s));
     HIP_TRY(launch_fill(d_dNT, bw, 0, s));
     HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
-    HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), (uint64_t)nB * Pn, 0, s));
+    HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), 2ull * nB * Pn, 0, s));
     HIP_TRY(launch_fill((uint64_t *)d_ctr, ring_words, 0, s));
     HIP_TRY(launch_seed_diag(d_T, tnz.as<uint64_t>(), n, P, Pn, tb.starts, nB, res.src_mask.as<uint64_t>(), s));
-    HIP_TRY(launch_eps(d_NT, d_dNT, dnt_act.as<uint64_t>(), o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
+    HIP_TRY(launch_eps(d_NT, d_dNT, dact[cur], o.keep_rank ? res.rank.as<uint8_t>() : nullptr, n, P,
                        Pn, tb.eps, (uint32_t)p.eps_boxes.size(), s));
+    if (use_nsum) {
+        HIP_TRY(launch_fill(nsum.as<uint64_t>(), (uint64_t)nB * n * sum_pitch, 0, s));
+        HIP_TRY(launch_row_summary(d_NT, nB, n, P, Pn, dact[cur], nsum.as<uint64_t>(), sum_pitch, s));
+    }
     // the seed's selectors (new nonterminal edges) are scanned once per source
     // tile: with long rows, a summary of their non-zero words, rebuilt after
     // every write-back, lets the scan skip the empty blocks
     DevBuf dsum;
-    const uint32_t sum_pitch = (Pn + kWave - 1) / kWave;
-    const bool use_sum = sparse_nt && Pn >= kSelSumMinWords;
+    const bool use_sum = sparse_nt;
     if (use_sum) {
         if (!dsum.alloc(al, (uint64_t)nB * n * sum_pitch * 8, s))
             return fail(CFPQ_ERR_OOM, "device allocation failed (selector summary)");
-        HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dnt_act.as<uint64_t>(), dsum.as<uint64_t>(), sum_pitch, s));
+        HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dact[cur], dsum.as<uint64_t>(), sum_pitch, s));
     }
 
     std::vector<uint64_t> box_delta(nB, 0);
@@ -738,6 +797,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             res.deltas.push_back(0);
             break;
         }
+        HIP_TRY(launch_fill(d_chg, aw, 0, s));   // rows gaining bits in this iteration
         if (scratch && it > 1) {   // forget the closure: only the box-start rows' own bits
             HIP_TRY(launch_fill(d_T, qw, 0, s));
             HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
@@ -746,39 +806,59 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         }
         for (uint32_t gi = 0; gi < groups; ++gi) {
             const uint32_t w0 = gi * G, gw = std::min(G, Pn - w0);
-            HIP_TRY(launch_fill(act[0], 3 * aw, 0, s));
+            HIP_TRY(launch_fill(act[0], 3 * aset, 0, s));
             GatherArgs a{};
             a.n = n; a.P = P; a.Pn = Pn; a.n_terms = p.n_terms; a.nQ = nQ;
             a.w0 = w0; a.gw = gw; a.G = G;
             a.goff = g.off.as<uint32_t>(); a.gidx = g.idx.as<uint32_t>();
             a.in_off = tb.in_off; a.in_tr = tb.in_tr;
-            a.T = d_T; a.tnz = tnz.as<uint64_t>(); a.ctr = d_ctr; a.clear_words = (uint32_t)aw;
+            a.T = d_T; a.tnz = tnz.as<uint64_t>(); a.ctr = d_ctr; a.clear_words = (uint32_t)aset;
+            a.Pbs = Pbs; a.chg = d_chg;
             // Kronecker product of the RSM with the new edges (seed); the seed
             // and the first chunk of levels always fit before a ring clear
             if ((st = need_slots(levels_hint + 2)) != CFPQ_OK) return st;
-            a.sel = scratch ? d_NT : d_dNT; a.sel_act = scratch ? ones.as<uint64_t>() : dnt_act.as<uint64_t>();
-            a.sel_sum = use_sum && !scratch ? dsum.as<uint64_t>() : nullptr; a.sum_pitch = sum_pitch;
+            a.sel = scratch ? d_NT : d_dNT; a.sel_act = scratch ? ones.as<uint64_t>() : dact[cur];
+            a.sel_sum = scratch ? (use_nsum ? nsum.as<uint64_t>() : nullptr) : (use_sum ? dsum.as<uint64_t>() : nullptr);
+            a.sum_pitch = sum_pitch;
             a.src = d_T; a.src_pitch = P; a.src_off = w0; a.src_act = tnz.as<uint64_t>();
-            a.dn = Dbuf[0]; a.actn = act[0]; a.act_clear = nullptr;
+            a.src_blk = nullptr;   // closure rows as sources: no coarse activity kept
+            a.dn = Dbuf[0]; a.actn = act[0]; a.actn_blk = blk[0]; a.act_clear = nullptr;
             a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1) || scratch;
-            a.extra = nullptr; a.extra_act = nullptr;
-            if ((st = prof_mark(0)) != CFPQ_OK) return st;   // the seed's time includes its sparse product
+            a.extra = nullptr; a.extra_act = nullptr; a.bytes_ctr = sp_bytes;
+            a.dense_apart = sparse_nt ? 1u : 0u;
+            if ((st = prof_mark3(0, 0)) != CFPQ_OK) return st;
             if (sparse_nt) {
                 // the product rows go to the other frontier buffer and the third
                 // activity bitset, both unused until the first level
                 uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
-                HIP_TRY(launch_ell_build(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt, ell_idx,
-                                         nullptr, Pn, nullptr, s));
+                HIP_TRY(launch_fill(d_dns, dense_words, 0, s));
+                HIP_TRY(launch_ell_build_dense(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt,
+                                               ell_idx, nullptr, Pn, nullptr, d_dns, d_dblk, Pbs, s));
+                if ((st = prof_mark3(0, 1)) != CFPQ_OK) return st;
                 HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dbuf[1], act[2], grid, s));
+                if ((st = prof_mark3(0, 3)) != CFPQ_OK) return st;
+                if ((st = dense_product(a, Dbuf[1], act[2])) != CFPQ_OK) return st;
                 a.extra = Dbuf[1]; a.extra_act = act[2];
+            } else {
+                if ((st = prof_mark3(0, 1)) != CFPQ_OK) return st;
+                if ((st = prof_mark3(0, 3)) != CFPQ_OK) return st;
             }
+            if ((st = prof_mark3(0, 2)) != CFPQ_OK) return st;
             const uint32_t seed_slot = slot;
             HIP_TRY(launch_gather(a, true, grid, s));
-            if ((st = prof_mark(1)) != CFPQ_OK) return st;
+            if ((st = prof_mark3(1, 0)) != CFPQ_OK) return st;
             if (prof) {
                 if ((st = fetch(seed_slot, 1)) != CFPQ_OK) return st;
                 res.prof[CFPQ_KERNEL_SEED].launches++;
-                res.prof[CFPQ_KERNEL_SEED].ms += prof_ms(0);
+                res.prof[CFPQ_KERNEL_SEED].ms += prof_span(ev3(0, 2), ev3(1, 0));
+                if (sparse_nt) {
+                    res.prof[CFPQ_KERNEL_ELL].launches++;
+                    res.prof[CFPQ_KERNEL_ELL].ms += prof_span(ev3(0, 0), ev3(0, 1));
+                    res.prof[CFPQ_KERNEL_NT_SPARSE].launches++;
+                    res.prof[CFPQ_KERNEL_NT_SPARSE].ms += prof_span(ev3(0, 1), ev3(0, 3));
+                    res.prof[CFPQ_KERNEL_NT_DENSE].launches++;
+                    res.prof[CFPQ_KERNEL_NT_DENSE].ms += prof_span(ev3(0, 3), ev3(0, 2));
+                }
             }
             uint32_t prev = slot++;
             uint64_t rows_in = prof ? pc.h[2] : 0;   // frontier rows feeding the next level
@@ -807,14 +887,17 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                         return fail(CFPQ_ERR_OOM, "device allocation failed (matrix-core product)");
                 }
                 for (uint32_t j = 0; j < k; ++j, ++li) {
-                    a.sel = d_NT; a.sel_act = nullptr; a.sel_sum = nullptr;
+                    a.sel = d_NT; a.sel_act = nullptr; a.sel_sum = use_nsum ? nsum.as<uint64_t>() : nullptr;
                     a.src = Dbuf[(li - 1) & 1]; a.src_pitch = G; a.src_off = 0;
-                    a.src_act = act[(li - 1) % 3];
-                    a.dn = Dbuf[li & 1]; a.actn = act[li % 3]; a.act_clear = act[(li + 1) % 3];
+                    a.src_act = act[(li - 1) % 3]; a.src_blk = blk[(li - 1) % 3];
+                    a.dn = Dbuf[li & 1]; a.actn = act[li % 3]; a.actn_blk = blk[li % 3];
+                    a.act_clear = act[(li + 1) % 3];
                     a.slot_prev = prev; a.slot_cur = slot; a.seed_terms = 0;
-                    if ((st = prof_mark2(j, 0)) != CFPQ_OK) return st;
+                    a.dense_apart = lsparse ? 1u : 0u;
+                    if ((st = prof_mark3(j, 0)) != CFPQ_OK) return st;
                     if (mfma) {
                         HIP_TRY(launch_fill(xact.as<uint64_t>(), aw, 0, s));
+                        if ((st = prof_mark3(j, 1)) != CFPQ_OK) return st;
                         std::vector<uint8_t> first(nQ, 1);
                         for (uint32_t f = 0; f < nQ; ++f)
                             for (uint32_t t = p.in_off[f]; t < p.in_off[f + 1]; ++t) {
@@ -833,23 +916,32 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                                 m.mfma_ctr = prof ? mfma_ops : nullptr;
                                 HIP_TRY(launch_nt_mfma(m, s));
                             }
+                        if ((st = prof_mark3(j, 3)) != CFPQ_OK) return st;
                         a.extra = Dx.as<uint64_t>(); a.extra_act = xact.as<uint64_t>();
                     } else if (lsparse) {
                         HIP_TRY(launch_fill(xact.as<uint64_t>(), aw, 0, s));
+                        HIP_TRY(launch_fill(d_dns, dense_words, 0, s));
                         uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
                         const unsigned long long *cp =
                             prev == kNoSlot ? nullptr : d_ctr + (uint64_t)prev * kSlotWords;
-                        HIP_TRY(launch_ell_build(a.src, G, 0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt,
-                                                 ell_idx, a.src_act, Pn, cp, s));
+                        HIP_TRY(launch_ell_build_dense(a.src, G, 0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(),
+                                                       ell_cnt, ell_idx, a.src_act, Pn, cp, d_dns, d_dblk, Pbs, s));
+                        if ((st = prof_mark3(j, 1)) != CFPQ_OK) return st;
                         a.extra = nullptr;   // the product reads the selector, not extra
                         HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dx.as<uint64_t>(), xact.as<uint64_t>(), grid, s));
+                        if ((st = prof_mark3(j, 3)) != CFPQ_OK) return st;
+                        if ((st = dense_product(a, Dx.as<uint64_t>(), xact.as<uint64_t>())) != CFPQ_OK) return st;
                         a.extra = Dx.as<uint64_t>(); a.extra_act = xact.as<uint64_t>();
+                    } else {
+                        if ((st = prof_mark3(j, 1)) != CFPQ_OK) return st;
+                        if ((st = prof_mark3(j, 3)) != CFPQ_OK) return st;
                     }
-                    if ((st = prof_mark2(j, 1)) != CFPQ_OK) return st;
+                    a.dense_apart = 0;
+                    if ((st = prof_mark3(j, 2)) != CFPQ_OK) return st;
                     HIP_TRY(launch_gather(a, false, grid, s));
                     prev = slot++;
                 }
-                if ((st = prof_mark2(k, 0)) != CFPQ_OK) return st;
+                if ((st = prof_mark3(k, 0)) != CFPQ_OK) return st;
                 if ((st = fetch(first_slot, k)) != CFPQ_OK) return st;
                 uint32_t used = k;
                 for (uint32_t j = 0; j < k; ++j)
@@ -861,11 +953,17 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                     auto &pl = res.prof[CFPQ_KERNEL_LEVEL];
                     for (uint32_t j = 0; j < k; ++j) {
                         pl.launches++;
-                        pl.ms += prof_span(2 + 2 * j + 1, 2 + 2 * (j + 1));
+                        pl.ms += prof_span(ev3(j, 2), ev3(j + 1, 0));
                         if (mfma || lsparse) {
                             auto &pp = res.prof[mfma ? CFPQ_KERNEL_NT_MFMA : CFPQ_KERNEL_NT_SPARSE];
                             pp.launches++;
-                            pp.ms += prof_span(2 + 2 * j, 2 + 2 * j + 1);
+                            pp.ms += prof_span(ev3(j, 1), ev3(j, 3));
+                        }
+                        if (lsparse) {
+                            res.prof[CFPQ_KERNEL_ELL].launches++;
+                            res.prof[CFPQ_KERNEL_ELL].ms += prof_span(ev3(j, 0), ev3(j, 1));
+                            res.prof[CFPQ_KERNEL_NT_DENSE].launches++;
+                            res.prof[CFPQ_KERNEL_NT_DENSE].ms += prof_span(ev3(j, 3), ev3(j, 2));
                         }
                         const uint64_t fed = pc.h[(size_t)j * kSlotWords + 1];
                         const uint64_t gained = pc.h[(size_t)j * kSlotWords + 2];
@@ -884,24 +982,26 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         }
         // write-back
         if ((st = need_slots(nB + 1)) != CFPQ_OK) return st;
-        HIP_TRY(launch_fill(dnt_act.as<uint64_t>(), (uint64_t)nB * Pn, 0, s));
+        HIP_TRY(launch_fill(dact[cur ^ 1], (uint64_t)nB * Pn, 0, s));
         WritebackArgs w{};
         w.n = n; w.P = P; w.Pn = Pn; w.nB = nB; w.fin_off = tb.fin_off; w.fin = tb.fin;
-        w.T = d_T; w.NT = d_NT; w.dNT = d_dNT; w.dnt_act = dnt_act.as<uint64_t>();
+        w.T = d_T; w.NT = d_NT; w.dNT = d_dNT; w.dnt_act = dact[cur ^ 1];
         w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
         w.iter = it; w.ctr = d_ctr; w.slot_base = slot;
+        w.chg = d_chg; w.prev_act = dact[cur]; w.rows_ctr = wb_rows;
         if ((st = prof_mark(0)) != CFPQ_OK) return st;
         HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
-        if (use_sum)
-            HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dnt_act.as<uint64_t>(), dsum.as<uint64_t>(), sum_pitch, s));
         if ((st = prof_mark(1)) != CFPQ_OK) return st;
+        cur ^= 1;
+        if (use_sum)
+            HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dact[cur], dsum.as<uint64_t>(), sum_pitch, s));
+        if (use_nsum)
+            HIP_TRY(launch_row_summary(d_NT, nB, n, P, Pn, dact[cur], nsum.as<uint64_t>(), sum_pitch, s));
         if ((st = fetch(slot, nB)) != CFPQ_OK) return st;
         if (prof) {
             auto &pw = res.prof[CFPQ_KERNEL_WRITEBACK];
             pw.launches++;
             pw.ms += prof_ms(0);
-            for (uint32_t b = 0; b < nB; ++b)
-                pw.bytes += 8ull * Pn * n * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + (p.fin_off[b + 1] > p.fin_off[b] ? 3 : 0));
         }
         slot += nB;
         uint64_t delta = 0;
@@ -918,10 +1018,18 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
     res.ms = ms;
     res.iterations = it;
-    if (mfma_ops) {
-        unsigned long long ops = 0;
-        HIP_TRY(hipMemcpy(&ops, mfma_ops, 8, hipMemcpyDeviceToHost));
-        res.prof[CFPQ_KERNEL_NT_MFMA].bytes = ops * 65536ull;   // 2 * 32 * 32 * 32 per instruction
+    if (prof) {
+        std::vector<unsigned long long> pc2(3 + nB);
+        HIP_TRY(hipMemcpy(pc2.data(), mfma_ops, pc2.size() * 8, hipMemcpyDeviceToHost));
+        res.prof[CFPQ_KERNEL_NT_MFMA].bytes = pc2[0] * 65536ull;   // 2 * 32 * 32 * 32 per instruction
+        res.prof[CFPQ_KERNEL_NT_SPARSE].bytes = pc2[1];
+        res.prof[CFPQ_KERNEL_NT_DENSE].bytes = pc2[2];
+        // write-back: per row visited, the final states' closure rows and
+        // the M2^N row read, M2^N and A2^N written (Pn words each)
+        auto &pw = res.prof[CFPQ_KERNEL_WRITEBACK];
+        pw.bytes = 0;
+        for (uint32_t b = 0; b < nB; ++b)
+            pw.bytes += pc2[3 + b] * 8ull * Pn * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + 3);
     }
     if (o.keep_blocks) res.T = std::move(T);
     return CFPQ_OK;
@@ -1857,7 +1965,7 @@ extern "C" cfpq_status cfpq_result_profile(cfpq_result r, uint32_t kind, uint64_
                                            uint64_t *bytes) {
     if (!r) return fail(CFPQ_ERR_INVALID, "result is NULL");
     if (!r->profiled) return fail(CFPQ_ERR_INVALID, "query was not profiled (opts.profile)");
-    if (kind > CFPQ_KERNEL_NT_SPARSE) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
+    if (kind > CFPQ_KERNEL_NT_DENSE) return fail(CFPQ_ERR_INVALID, "unknown kernel kind");
     if (launches) *launches = r->prof[kind].launches;
     if (ms) *ms = r->prof[kind].ms;
     if (bytes) *bytes = r->prof[kind].bytes;

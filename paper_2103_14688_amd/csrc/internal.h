@@ -68,9 +68,20 @@ struct GatherArgs {
     const uint64_t *sel_sum;      // optional summary of the selector rows: bit w of row word w / 64
                                   // set iff selector word w may be non-zero, [rows][sum_pitch]
     uint32_t sum_pitch;
+    // optional coarse activity of the source rows, [nQ][Pbs]: bit j % 64 of
+    // word j / 64 set iff src_act word j may be non-zero, word Pbs - 1
+    // non-zero iff the state may have an active row; actn_blk: the same for
+    // the next frontier (cleared with actn); Pbs = sum_pitch + 1
+    const uint64_t *src_blk;
+    uint64_t *actn_blk;
+    uint32_t Pbs;
+    uint64_t *chg;                // optional: rows that gained bits in this iteration, [nQ][Pn]
+    unsigned long long *bytes_ctr; // optional (profiling): bytes of the words the launch reads and writes
+    // sparse product: source rows listed as dense (more than kEll bits) are
+    // left to k_nt_dense; every target row with a selected source row is
+    // still written and flagged (the dense product ORs into it afterwards)
+    uint32_t dense_apart;
 };
-// selector summaries pay from this many words per row on
-constexpr uint32_t kSelSumMinWords = 1024;
 // summary of the rows [nB][n][P] whose bit is set in act ([nB][Pn] bits;
 // other rows' summaries are left as they are): bit w % 64 of summary word
 // w / 64 set iff word w is non-zero
@@ -82,6 +93,12 @@ hipError_t launch_row_summary(const uint64_t *rows, uint32_t nB, uint32_t n, uin
 #endif
 constexpr uint32_t kEll = CFPQ_ELL;            // listed bits per source row in the sparse product (tuning)
 constexpr uint32_t kEllDense = 0xFFFFFFFFu;    // row has more bits: OR it whole
+constexpr uint32_t kEllBlocked = 0xFFFFFFFEu;  // row beyond a list, left to the LDS-blocked product
+// (kEllDense rows are ORed whole by the sparse product itself: only where
+// no dense product runs, the matrix-core and whole-row modes.  ORing rows
+// of 33 to 1/8 of the tile's bits whole per target measured 2-4x slower
+// than the blocked product on random dense grammars)
+static_assert(kEll >= 2, "a dense row's list holds its 64-bit block mask");
 // closure levels use the sparse product from this many words per row tile
 // (narrower rows are ORed whole at no greater cost)
 constexpr uint32_t kLevelSparseMinWords = 16;
@@ -105,6 +122,13 @@ struct WritebackArgs {
     const uint32_t *state_flags;   // optional (with multi): rows of single-member components of a
     const uint32_t *multi;         //   kAliasFinal state are already in NT; such rows are skipped
     const unsigned long long *skip_if[2];   // optional: the launch does nothing if either is nonzero
+    // optional (levels strategy): only rows (N, v) with chg[f][v] set for a
+    // final state f of N (its closure row gained bits in this iteration) or
+    // with prev_act[N][v] set (their dNT row is not yet cleared) are visited;
+    // every other row of NT and dNT is already what the write-back would leave
+    const uint64_t *chg;
+    const uint64_t *prev_act;
+    unsigned long long *rows_ctr;  // optional (profiling): rows visited, per box [nB]
 };                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip
@@ -126,9 +150,30 @@ hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStrea
 // bit is clear, may be null; ctr_prev: skip the launch when that count is 0)
 hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
                             const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
-                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s);
+                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s,
+                            unsigned long long *bytes_ctr = nullptr);
 hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const uint32_t *ell_idx, uint64_t *extra,
                             uint64_t *extra_act, uint32_t grid, hipStream_t s);
+// Dense part of the nonterminal product: the source rows the ELL build
+// listed as dense (dns [nQ][Pn] bits, their coarse array dblk [nQ][Pbs]),
+// blocked through LDS: a workgroup owns 128 target rows x 64 source words
+// and ORs each staged block of 64 source rows into all of them.  Runs after
+// k_nt_sparse (with dense_apart), ORing into the product rows it flagged.
+struct DenseArgs {
+    const uint64_t *dns, *dblk;
+    const uint32_t *ell_idx;       // a dense row's list holds the 64-bit mask of its non-zero 64-word blocks
+    const uint32_t *nt_dst;        // target states of box-labelled transitions
+    uint32_t n_nt_dst;
+    uint64_t *extra;               // product rows [nQ][n][G]
+    const uint64_t *extra_act;     // [nQ][Pn], flagged by k_nt_sparse
+};
+hipError_t launch_nt_dense(const GatherArgs &a, const DenseArgs &d, hipStream_t s);
+// ELL build also marks dense rows: dns bit and coarse dblk (both pre-cleared)
+hipError_t launch_ell_build_dense(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
+                                  const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
+                                  const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev,
+                                  uint64_t *dns, uint64_t *dblk, uint32_t Pbs, hipStream_t s,
+                                  unsigned long long *bytes_ctr = nullptr);
 
 // Dense nonterminal product of one transition (s, N, f) on the matrix cores.
 struct MfmaArgs {

@@ -21,6 +21,12 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int o) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
     for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
     return x;
@@ -55,6 +61,25 @@ __device__ __forceinline__ void block_add(unsigned long long *c0, unsigned long 
 
 __device__ __forceinline__ bool test_bit(const uint64_t *bits, uint32_t i) {
     return (bits[i >> 6] >> (i & 63)) & 1ull;
+}
+
+// Row v of state f became active: its word's bit in the coarse activity
+// array blk ([nQ][Pbs], see GatherArgs) and the state's any-word.  Each is
+// read first and written only if not yet set, so the many rows of one block
+// or state do not all meet on one address.
+__device__ __forceinline__ void mark_blk(uint64_t *blk, uint32_t Pbs, uint32_t f, uint32_t v) {
+    uint64_t *b = blk + (uint64_t)f * Pbs;
+    const uint32_t w = v >> 6;
+    const uint64_t bit = 1ull << (w & 63);
+    if (!(__hip_atomic_load(&b[w >> 6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+        atomicOr((unsigned long long *)&b[w >> 6], bit);
+    if (!__hip_atomic_load(&b[Pbs - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        __hip_atomic_store(&b[Pbs - 1], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Whether state s may have an active source row (no coarse array: yes).
+__device__ __forceinline__ bool state_live(const GatherArgs &a, uint32_t s) {
+    return !a.src_blk || a.src_blk[(uint64_t)s * a.Pbs + a.Pbs - 1] != 0;
 }
 
 // SplitMix64 output function (Steele, Lea, Flood 2014): the generator's first
@@ -212,12 +237,16 @@ hipError_t launch_eps(uint64_t *NT, uint64_t *dNT, uint64_t *dnt_act, uint8_t *r
 // ---------------------------------------------------------------------------
 // closure row: the core of both the Kronecker seeding and a closure level
 // ---------------------------------------------------------------------------
+// by: bytes this lane read (profiling count)
 __device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t *row,
-                                       uint32_t pass0, uint32_t gw, int lane) {
+                                       uint32_t pass0, uint32_t gw, int lane, unsigned long long &by) {
 #pragma unroll
     for (int c = 0; c < kChunks; ++c) {
         uint32_t w = pass0 + c * kWave + lane;
-        if (w < gw) acc[c] |= row[c * kWave + lane];
+        if (w < gw) {
+            acc[c] |= row[c * kWave + lane];
+            by += 8;
+        }
     }
 }
 
@@ -233,7 +262,7 @@ __device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t 
 // new bits to cnt (per lane); fed tells whether any source row fed the row.
 template <bool SEED>
 __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned long long &cnt,
-                           bool &fed) {
+                           bool &fed, unsigned long long &by) {
     const int lane = __lane_id();
     const uint32_t tb = a.in_off[f], te = a.in_off[f + 1];
     fed = false;
@@ -247,6 +276,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
             const InTrans tr = a.in_tr[t];
             const uint64_t *rows = a.src + (uint64_t)tr.src * a.n * a.src_pitch + a.src_off + pass0;
             const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
+            if (!state_live(a, tr.src)) continue;   // no active row in the source state
             if (tr.sym < a.n_terms) {
                 if (SEED && !a.seed_terms) continue;
                 const uint32_t *op = a.goff + (uint64_t)tr.sym * (a.n + 1) + v;
@@ -264,7 +294,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                         const int j = __ffsll((unsigned long long)m) - 1;
                         m &= m - 1;
                         const uint32_t xj = (uint32_t)__builtin_amdgcn_readlane((int)x, j);
-                        or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane);
+                        or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane, by);
                     }
                 }
             } else {
@@ -272,10 +302,17 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                 const uint32_t N = tr.sym - a.n_terms;
                 if (SEED && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
                 const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
+                const uint64_t *ssum = a.sel_sum ? a.sel_sum + ((uint64_t)N * a.n + v) * a.sum_pitch : nullptr;
+                const uint64_t *sblk = a.src_blk ? a.src_blk + (uint64_t)tr.src * a.Pbs : nullptr;
                 for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
                     const uint32_t k = k0 + lane;
+                    // 64 words at once: only where the selector row and the
+                    // source activity may both be non-zero
+                    uint64_t live = ssum ? ssum[k0 / kWave] : ~0ull;
+                    if (sblk) live &= sblk[k0 / kWave];
+                    if (!live) continue;
                     uint64_t wb = 0;
-                    if (k < a.Pn) {
+                    if (k < a.Pn && ((live >> lane) & 1ull)) {
                         // the activity word first: the selector is read only
                         // where some source row is live
                         const uint64_t sa = sact[k];
@@ -291,7 +328,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                             const int bb = __ffsll((unsigned long long)bits) - 1;
                             bits &= bits - 1;
                             const uint32_t xj = (k0 + (uint32_t)j) * 64u + (uint32_t)bb;
-                            or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane);
+                            or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane, by);
                         }
                     }
                 }
@@ -299,7 +336,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
         }
         if (a.extra && test_bit(a.extra_act + (uint64_t)f * a.Pn, v)) {
             fed = true;
-            or_row(acc, a.extra + ((uint64_t)f * a.n + v) * a.G + pass0, pass0, a.gw, lane);
+            or_row(acc, a.extra + ((uint64_t)f * a.n + v) * a.G + pass0, pass0, a.gw, lane, by);
         }
         if (!fed) return false;  // no source row feeds (f, v): same in every pass
         uint64_t *trow = a.T + ((uint64_t)f * a.n + v) * a.P + a.w0 + pass0;
@@ -317,6 +354,7 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     cnt += (unsigned long long)__popcll(nw);
                 }
                 drow[c * kWave + lane] = nw;
+                by += nw ? 24 : 16;   // T read, frontier written, T written if it grew
             }
         }
         row_new |= (__ballot(any) != 0);
@@ -346,11 +384,14 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x) {
 __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw,
                                                       uint32_t n, const uint32_t *states, uint32_t n_states,
                                                       uint32_t *ell_cnt, uint32_t *ell_idx, const uint64_t *act,
-                                                      uint32_t Pn, const unsigned long long *ctr_prev) {
+                                                      uint32_t Pn, const unsigned long long *ctr_prev,
+                                                      unsigned long long *bytes_ctr, uint64_t *dns, uint64_t *dblk,
+                                                      uint32_t Pbs) {
     if (ctr_prev && *ctr_prev == 0) return;  // the frontier ran dry
     const int lane = __lane_id();
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long by = 0;   // profiling: bytes read and written by this lane
     for (uint64_t r = wave; r < (uint64_t)n_states * n; r += nwaves) {
         const uint32_t s = states[r / n], x = (uint32_t)(r % n);
         // rows marked inactive are never looked up (the product tests the
@@ -358,12 +399,30 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
         if (act && !test_bit(act + (uint64_t)s * Pn, x)) continue;
         const uint64_t *row = rows + ((uint64_t)s * n + x) * pitch + off;
         uint32_t mine = 0;
-        for (uint32_t w = lane; w < gw; w += kWave) mine += (uint32_t)__popcll(row[w]);
+        uint64_t bmask = 0;   // bit c: words [64 c, 64 c + 64) of the row's tile hold a bit
+        for (uint32_t c = 0, w = lane; c * kWave < gw; ++c, w += kWave) {
+            const uint64_t x_w = w < gw ? row[w] : 0ull;
+            mine += (uint32_t)__popcll(x_w);
+            if (__ballot(x_w != 0)) bmask |= 1ull << (c & 63);
+            by += w < gw ? 8 : 0;
+        }
         uint32_t total = mine;
         for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o, kWave);
         const uint64_t cell = (uint64_t)s * n + x;
+        by += 4ull * mine + (lane == 0 ? 4 : 0);
         if (total > kEll) {
-            if (lane == 0) ell_cnt[cell] = kEllDense;
+            if (lane == 0) {
+                const bool blocked = dns != nullptr;
+                ell_cnt[cell] = blocked ? kEllBlocked : kEllDense;
+                if (blocked) {
+                    atomicOr((unsigned long long *)&dns[(uint64_t)s * Pn + (x >> 6)], 1ull << (x & 63));
+                    mark_blk(dblk, Pbs, s, x);
+                    // a dense row's list holds its block mask instead (two
+                    // 32-bit entries: the list is only 4-byte aligned)
+                    ell_idx[cell * kEll] = (uint32_t)bmask;
+                    ell_idx[cell * kEll + 1] = (uint32_t)(bmask >> 32);
+                }
+            }
             continue;
         }
         uint32_t at = wave_excl_scan(mine);
@@ -377,6 +436,10 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
             }
         }
         if (lane == 0) ell_cnt[cell] = total;
+    }
+    if (bytes_ctr) {
+        by = wave_sum(by);
+        if (lane == 0 && by) atomicAdd(bytes_ctr, by);
     }
 }
 
@@ -408,6 +471,8 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
 #endif
     constexpr int kDenseRows = CFPQ_DENSE_ROWS;   // rows in flight per step (tuning parameter)
     const uint32_t gw_reg = a.gw < kDenseRegs * kWave ? a.gw : kDenseRegs * kWave;
+    // profiling: bytes of the words this wavefront reads and writes (per lane)
+    unsigned long long by = 0;
     for (uint64_t r = wave; r < (uint64_t)a.nQ * a.n; r += nwaves) {
         const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
         bool cleared = false, any = false;
@@ -418,14 +483,18 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             const InTrans tr = a.in_tr[t];
             if (tr.sym < a.n_terms) continue;
             const uint32_t N = tr.sym - a.n_terms;
+            if (!state_live(a, tr.src)) continue;   // no active row in the source state
             if (a.sel_act && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
             const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
             const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
             const uint64_t *ssum = a.sel_sum ? a.sel_sum + ((uint64_t)N * a.n + v) * a.sum_pitch : nullptr;
+            const uint64_t *sblk = a.src_blk ? a.src_blk + (uint64_t)tr.src * a.Pbs : nullptr;
             for (uint32_t k0 = 0; k0 < a.Pn; k0 += kWave) {
                 const uint32_t k = k0 + lane;
-                // with a summary, only words that may be non-zero are read
-                const uint64_t live = ssum ? ssum[k0 / kWave] : ~0ull;
+                // with a summary of the selector row and the coarse source
+                // activity, only words where both may be non-zero are read
+                uint64_t live = ssum ? ssum[k0 / kWave] : ~0ull;
+                if (sblk) live &= sblk[k0 / kWave];
                 if (!live) continue;
                 uint64_t wb = 0;
                 if (k < a.Pn && ((live >> lane) & 1ull)) {
@@ -433,6 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                     // where some source row is live
                     const uint64_t sa = sact[k];
                     if (sa) wb = sel[k] & sa;
+                    by += sa ? 16 : 8;
                 }
                 uint64_t m = __ballot(wb != 0);
                 if (m && !cleared) {
@@ -452,15 +522,20 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                     const bool mine = (bits >> lane) & 1ull;
                     const uint64_t cell = (uint64_t)tr.src * a.n + xb + (uint32_t)lane;
                     const uint32_t cnt = mine ? ell_cnt[cell] : 0u;
-                    const bool dense = cnt == kEllDense;
-                    if (!dense) {
+                    // rows beyond an ELL list: ORed whole here, unless they are
+                    // left to the blocked dense product
+                    const bool dense = cnt == kEllDense || (cnt == kEllBlocked && !a.dense_apart);
+                    const bool apart = cnt == kEllBlocked && a.dense_apart;
+                    if (!dense && !apart) {
                         const uint32_t *idx = ell_idx + cell * kEll;
                         for (uint32_t e = 0; e < cnt; ++e) {
                             const uint32_t u = idx[e];
                             atomicOr(&acc[u >> 6], 1ull << (u & 63));
                         }
                     }
+                    if (mine) by += 4ull * (1 + (dense || apart ? 0u : cnt));
                     uint64_t dm = __ballot(dense);
+                    if (lane == 0) by += 8ull * a.gw * (uint64_t)__popcll(dm);
                     const uint64_t *rbase = a.src + ((uint64_t)tr.src * a.n + xb) * a.src_pitch + a.src_off;
                     while (dm) {
                         const uint64_t *rr[kDenseRows];
@@ -507,19 +582,39 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             const uint64_t x = acc[w];
             out[w] = x;
             nz |= x != 0;
+            by += 8;
         }
-        if (__ballot(nz) && lane == 0)
+        // with dense rows apart the row is flagged even if still zero: the
+        // dense product ORs into flagged rows only
+        if ((a.dense_apart || __ballot(nz)) && lane == 0)
             atomicOr((unsigned long long *)&extra_act[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
         __builtin_amdgcn_wave_barrier();
+    }
+    if (a.bytes_ctr) {
+        by = wave_sum(by);
+        if (lane == 0 && by) atomicAdd(a.bytes_ctr, by);
     }
 }
 
 hipError_t launch_ell_build(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
                             const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
-                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s) {
+                            const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev, hipStream_t s,
+                            unsigned long long *bytes_ctr) {
     if (!n_states) return hipSuccess;
     hipLaunchKernelGGL(k_ell_build, dim3(grid_for((uint64_t)n_states * n * kWave)), dim3(kBlock), 0, s, rows, pitch,
-                       off, gw, n, states, n_states, ell_cnt, ell_idx, act, Pn, ctr_prev);
+                       off, gw, n, states, n_states, ell_cnt, ell_idx, act, Pn, ctr_prev, bytes_ctr, nullptr,
+                       nullptr, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_ell_build_dense(const uint64_t *rows, uint32_t pitch, uint32_t off, uint32_t gw, uint32_t n,
+                                  const uint32_t *states, uint32_t n_states, uint32_t *ell_cnt, uint32_t *ell_idx,
+                                  const uint64_t *act, uint32_t Pn, const unsigned long long *ctr_prev,
+                                  uint64_t *dns, uint64_t *dblk, uint32_t Pbs, hipStream_t s,
+                                  unsigned long long *bytes_ctr) {
+    if (!n_states) return hipSuccess;
+    hipLaunchKernelGGL(k_ell_build, dim3(grid_for((uint64_t)n_states * n * kWave)), dim3(kBlock), 0, s, rows, pitch,
+                       off, gw, n, states, n_states, ell_cnt, ell_idx, act, Pn, ctr_prev, bytes_ctr, dns, dblk, Pbs);
     return hipGetLastError();
 }
 
@@ -527,6 +622,153 @@ hipError_t launch_nt_sparse(const GatherArgs &a, const uint32_t *ell_cnt, const 
                             uint64_t *extra_act, uint32_t grid, hipStream_t s) {
     const size_t lds = (size_t)(kBlock / kWave) * a.gw * 8;
     hipLaunchKernelGGL(k_nt_sparse, dim3(grid), dim3(kBlock), lds, s, a, ell_cnt, ell_idx, extra, extra_act);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// dense nonterminal product, blocked through LDS.  For every transition
+// (s, N, f) and target row (f, v):
+//   extra[f][v] |= OR over dense source rows x of s with N(x, v): src[s][x]
+// A workgroup owns a task (f, 128 consecutive targets v, 64 source words):
+// wavefront w holds targets 32 w .. 32 w + 31 of the block, lane i the
+// source word u0 + i, one accumulator word per target.  Per word xw of the
+// selector (64 source rows x), if any of the block's targets selects one of
+// the dense rows there, those rows' 64-word slices are staged in LDS once
+// and ORed into every target that selects them: each source word read from
+// memory serves up to 128 targets instead of one.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDenseTargets = 128;      // target rows per workgroup
+constexpr uint32_t kDenseTPW = kDenseTargets / (kBlock / kWave);   // per wavefront
+
+__device__ __forceinline__ bool dense_live(const uint64_t *dblk, uint32_t Pbs, uint32_t s) {
+    return dblk[(uint64_t)s * Pbs + Pbs - 1] != 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_nt_dense(GatherArgs a, DenseArgs d) {
+    if (a.slot_prev != kNoSlot && a.ctr[(uint64_t)a.slot_prev * kSlotWords] == 0) return;  // frontier ran dry
+    __shared__ uint64_t tile[64][kWave];
+    __shared__ uint64_t s_rows[kBlock / kWave];
+    const int lane = __lane_id();
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t nvb = (a.n + kDenseTargets - 1) / kDenseTargets, nub = (a.gw + kWave - 1) / kWave;
+    const uint64_t tasks = (uint64_t)d.n_nt_dst * nvb * nub;
+    unsigned long long by = 0;
+    for (uint64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+        // targets fastest: consecutive workgroups share the staged source slice
+        const uint32_t vb = (uint32_t)(task % nvb), ub = (uint32_t)((task / nvb) % nub);
+        const uint32_t f = d.nt_dst[task / ((uint64_t)nvb * nub)];
+        const uint32_t v0 = vb * kDenseTargets + w * kDenseTPW, u = ub * kWave + (uint32_t)lane;
+        uint64_t acc[kDenseTPW];
+#pragma unroll
+        for (uint32_t t = 0; t < kDenseTPW; ++t) acc[t] = 0;
+        bool touched = false;
+        for (uint32_t tr_i = a.in_off[f]; tr_i < a.in_off[f + 1]; ++tr_i) {
+            const InTrans tr = a.in_tr[tr_i];
+            if (tr.sym < a.n_terms) continue;
+            const uint32_t sst = tr.src, N = tr.sym - a.n_terms;
+            if (!dense_live(d.dblk, a.Pbs, sst)) continue;   // no dense source row in state s
+            // lane t < 32 of each wavefront: selector row of its target v0 + t
+            const uint32_t my_v = v0 + (uint32_t)(lane & 31);
+            const bool v_ok = lane < (int)kDenseTPW && my_v < a.n &&
+                              (!a.sel_act || test_bit(a.sel_act + (uint64_t)N * a.Pn, my_v));
+            const uint64_t *sel = a.sel + ((uint64_t)N * a.n + my_v) * a.P;
+            const uint64_t *ssum = a.sel_sum ? a.sel_sum + ((uint64_t)N * a.n + my_v) * a.sum_pitch : nullptr;
+            const uint64_t *dbk = d.dblk + (uint64_t)sst * a.Pbs;
+            const uint64_t *dn = d.dns + (uint64_t)sst * a.Pn;
+            const uint64_t *rows = a.src + (uint64_t)sst * a.n * a.src_pitch + a.src_off;
+            for (uint32_t xb = 0; xb + 1 < a.Pbs; ++xb) {
+                uint64_t mwb = dbk[xb];   // x-words of this group holding dense rows
+                if (!mwb) continue;
+                if (ssum) {
+                    // only x-words some target of the block may select (from the
+                    // selector rows' summaries): one word per target per group
+                    uint64_t us = v_ok ? ssum[xb] : 0ull;
+                    by += v_ok ? 8 : 0;
+                    for (int o = 32; o > 0; o >>= 1) us |= shfl_xor64(us, o);
+                    if (lane == 0) s_rows[w] = us;
+                    __syncthreads();
+                    uint64_t u_all = 0;
+#pragma unroll
+                    for (uint32_t i = 0; i < kBlock / kWave; ++i) u_all |= s_rows[i];
+                    __syncthreads();   // s_rows is reused below
+                    mwb &= u_all;
+                }
+                for (uint64_t mw = mwb; mw; mw &= mw - 1) {
+                    const uint32_t xw = xb * 64 + (uint32_t)(__ffsll((unsigned long long)mw) - 1);
+                    const uint64_t mx = dn[xw];   // dense source rows x = 64 xw + j
+                    if (!mx) continue;
+                    const uint64_t sw = v_ok ? (sel[xw] & mx) : 0ull;
+                    by += v_ok ? 8 : 0;
+                    // rows some target of the block selects whose slice of
+                    // this workgroup's 64 source words holds a bit (block
+                    // masks from the ELL build)
+                    uint64_t wu = sw;
+                    for (int o = 32; o > 0; o >>= 1) wu |= shfl_xor64(wu, o);
+                    uint64_t mine_rows = 0;
+                    if (lane < 64) {
+                        const uint32_t j = (uint32_t)lane;
+                        if ((wu >> j) & 1ull) {
+                            const uint32_t *li = d.ell_idx + ((uint64_t)sst * a.n + xw * 64 + j) * kEll;
+                            const uint64_t bm = (uint64_t)li[0] | ((uint64_t)li[1] << 32);
+                            if ((bm >> (ub & 63)) & 1ull) mine_rows = 1ull << j;
+                        }
+                    }
+                    const uint64_t wave_rows = __ballot(mine_rows != 0);
+                    if (lane == 0) s_rows[w] = wave_rows;
+                    __syncthreads();
+                    uint64_t staged = 0;
+#pragma unroll
+                    for (uint32_t i = 0; i < kBlock / kWave; ++i) staged |= s_rows[i];
+                    if (staged) {
+                        // wavefront w stages rows j (k-th set bit of staged) with k % 4 == w
+                        uint64_t rem = staged;
+                        for (uint32_t k = 0; rem; ++k, rem &= rem - 1) {
+                            if ((k & 3) != w) continue;
+                            const uint32_t j = (uint32_t)(__ffsll((unsigned long long)rem) - 1);
+                            const uint64_t *row = rows + (uint64_t)(xw * 64 + j) * a.src_pitch;
+                            tile[j][lane] = u < a.gw ? row[u] : 0ull;
+                            by += u < a.gw ? 8 : 0;
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (uint32_t t = 0; t < kDenseTPW; ++t) {
+                            uint64_t bits = readlane64(sw, (int)t) & staged;
+                            while (bits) {
+                                const int j = __ffsll((unsigned long long)bits) - 1;
+                                bits &= bits - 1;
+                                acc[t] |= tile[j][lane];
+                            }
+                        }
+                        touched = true;
+                    }
+                    __syncthreads();   // s_rows and the tile are reused
+                }
+            }
+        }
+        if (touched && u < a.gw) {
+#pragma unroll
+            for (uint32_t t = 0; t < kDenseTPW; ++t) {
+                const uint32_t v = v0 + t;
+                if (v < a.n && acc[t] && test_bit(d.extra_act + (uint64_t)f * a.Pn, v)) {
+                    uint64_t *o = d.extra + ((uint64_t)f * a.n + v) * a.G + u;
+                    *o |= acc[t];
+                    by += 16;
+                }
+            }
+        }
+    }
+    if (a.bytes_ctr) {
+        by = wave_sum(by);
+        if (lane == 0 && by) atomicAdd(a.bytes_ctr, by);
+    }
+}
+
+hipError_t launch_nt_dense(const GatherArgs &a, const DenseArgs &d, hipStream_t s) {
+    const uint64_t tasks = (uint64_t)d.n_nt_dst * ((a.n + kDenseTargets - 1) / kDenseTargets) *
+                           ((a.gw + kWave - 1) / kWave);
+    if (!tasks) return hipSuccess;
+    const uint64_t grid = tasks < 256 * 8 ? tasks : 256 * 8;
+    hipLaunchKernelGGL(k_nt_dense, dim3((uint32_t)grid), dim3(kBlock), 0, s, a, d);
     return hipGetLastError();
 }
 
@@ -656,14 +898,16 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
         for (uint64_t i = gtid; i < a.clear_words; i += gthreads) a.act_clear[i] = 0;
     const int lane = __lane_id();
     const uint64_t wave = gtid >> 6, nwaves = gthreads >> 6;
-    unsigned long long cnt = 0, fed_rows = 0, new_rows = 0;
+    unsigned long long cnt = 0, fed_rows = 0, new_rows = 0, by = 0;
     const uint64_t rows = (uint64_t)a.nQ * a.n;
     for (uint64_t r = wave; r < rows; r += nwaves) {
         const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
         bool fed = false;
-        if (gather_row<SEED>(a, f, v, cnt, fed) && lane == 0) {
+        if (gather_row<SEED>(a, f, v, cnt, fed, by) && lane == 0) {
             atomicOr((unsigned long long *)&a.actn[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
             atomicOr((unsigned long long *)&a.tnz[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
+            if (a.actn_blk) mark_blk(a.actn_blk, a.Pbs, f, v);
+            if (a.chg) atomicOr((unsigned long long *)&a.chg[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
             ++new_rows;
         }
         fed_rows += fed ? 1 : 0;
@@ -671,6 +915,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
     // new bits per lane; rows fed and rows gaining bits once per wavefront
     unsigned long long *c = a.ctr + (uint64_t)a.slot_cur * kSlotWords;
     block_add(&c[0], cnt, &c[1], lane == 0 ? fed_rows : 0ull, &c[2], lane == 0 ? new_rows : 0ull);
+    if (a.bytes_ctr) {
+        by = wave_sum(by);
+        if (lane == 0 && by) atomicAdd(a.bytes_ctr, by);
+    }
 }
 
 hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStream_t s) {
@@ -730,10 +978,10 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
     if ((a.skip_if[0] && *a.skip_if[0]) || (a.skip_if[1] && *a.skip_if[1])) return;
     // new edges per box: summed per workgroup in LDS (rows of one box meet
     // on one counter), flushed with one atomic per box and workgroup
-    __shared__ unsigned long long s_box[kWbLdsBoxes];
+    __shared__ unsigned long long s_box[kWbLdsBoxes], s_rows[kWbLdsBoxes];
     const bool lds_boxes = a.nB <= kWbLdsBoxes;
     if (lds_boxes)
-        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x) s_box[i] = 0;
+        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x) s_box[i] = s_rows[i] = 0;
     __syncthreads();
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
@@ -752,6 +1000,12 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
         bool any = false;
         writeback_row(a, N, v, c, any);
         c = wave_sum(c);
+        if (a.rows_ctr && lane == 0) {
+            if (lds_boxes)
+                atomicAdd(&s_rows[N], 1ull);
+            else
+                atomicAdd(&a.rows_ctr[N], 1ull);
+        }
         if (lane == 0 && any) {
             if (a.dnt_act)
                 atomicOr((unsigned long long *)&a.dnt_act[(uint64_t)N * a.Pn + (v >> 6)], 1ull << (v & 63));
@@ -761,8 +1015,23 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
                 atomicAdd(&a.ctr[(uint64_t)(a.slot_base + N) * kSlotWords], c);
         }
     };
-    if (!a.state_flags)
+    if (!a.state_flags && !a.chg)
         for (uint64_t r = wave; r < rows; r += nwaves) one_row(r);
+    // levels strategy: a lane per row finds the rows whose final-state closure
+    // rows gained bits in this iteration or whose dNT row still holds the
+    // previous iteration's edges, 64 rows at a time
+    for (uint64_t r0 = wave * kWave; !a.state_flags && a.chg && r0 < rows; r0 += nwaves * kWave) {
+        const uint64_t r = r0 + (uint64_t)lane;
+        bool need = false;
+        if (r < rows) {
+            const uint32_t N = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
+            need = a.prev_act && test_bit(a.prev_act + (uint64_t)N * a.Pn, v);
+            for (uint32_t i = a.fin_off[N]; !need && i < a.fin_off[N + 1]; ++i)
+                need = test_bit(a.chg + (uint64_t)a.fin[i] * a.Pn, v);
+        }
+        for (uint64_t todo = __ballot(need); todo; todo &= todo - 1)
+            one_row(r0 + (uint64_t)(__ffsll((unsigned long long)todo) - 1));
+    }
     // condensed closure: most answer rows were written (and counted) by the
     // closure itself; a lane per row finds the others, 64 rows at a time
     for (uint64_t r0 = wave * kWave; a.state_flags && r0 < rows; r0 += nwaves * kWave) {
@@ -781,8 +1050,10 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
     }
     if (lds_boxes) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x)
+        for (uint32_t i = threadIdx.x; i < a.nB; i += blockDim.x) {
             if (s_box[i]) atomicAdd(&a.ctr[(uint64_t)(a.slot_base + i) * kSlotWords], s_box[i]);
+            if (a.rows_ctr && s_rows[i]) atomicAdd(&a.rows_ctr[i], s_rows[i]);
+        }
     }
 }
 
@@ -1012,12 +1283,16 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     a.act_clear = nullptr; a.clear_words = 0; a.ctr = nullptr;
     a.slot_prev = kNoSlot; a.slot_cur = 0;
     a.extra = nullptr; a.extra_act = nullptr;
+    a.sel_sum = nullptr; a.sum_pitch = 0;
+    a.src_blk = nullptr; a.actn_blk = nullptr; a.Pbs = 0; a.chg = nullptr; a.bytes_ctr = nullptr;
+    a.dense_apart = 0;
 
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
     wb.T = Q.T; wb.NT = Q.NT; wb.dNT = Q.dNT; wb.dnt_act = Q.dnt_act; wb.rank = Q.rank;
     wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr; wb.fresh = 0; wb.row_nz = nullptr;
     wb.state_flags = nullptr; wb.multi = nullptr; wb.skip_if[0] = wb.skip_if[1] = nullptr;
+    wb.chg = nullptr; wb.prev_act = nullptr; wb.rows_ctr = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     const bool narrow = Q.Pn <= kNarrowWords;
@@ -1053,7 +1328,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
             for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
                 const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
                 bool fed;
-                if (gather_row<true>(a, f, v, cnt, fed) && lane == 0) {
+                unsigned long long by = 0;
+                if (gather_row<true>(a, f, v, cnt, fed, by) && lane == 0) {
                     atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                     atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                 }
@@ -1085,7 +1361,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
                 for (uint64_t r = wave; r < (uint64_t)Q.nQ * Q.n; r += nwaves) {
                     const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
                     bool fed;
-                    if (gather_row<false>(a, f, v, cnt, fed) && lane == 0) {
+                    unsigned long long by = 0;
+                    if (gather_row<false>(a, f, v, cnt, fed, by) && lane == 0) {
                         atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                         atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                     }
