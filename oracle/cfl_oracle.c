@@ -399,32 +399,29 @@ int oracle_rpq_rows(uint32_t n, uint64_t m, const uint32_t *src, const uint32_t 
  *    adds what the unit and binary rules derive from facts of which at least
  *    one is new in round k (semi-naive evaluation: a pair of two older facts
  *    was already composed in an earlier round); it stops when a round adds
- *    nothing.  Every relation is an n x n bitset (row u: the v with (u, v));
- *    so memory is 3 n^2/8 bytes per nonterminal (relation, last round's new
- *    facts, this round's new facts).  Rows of one composition are computed in
- *    parallel on `threads` threads.  rounds (optional) receives the number of
- *    rounds, the last (empty) one included.
+ *    nothing.  Every relation is an n x n bitset (row u: the v with (u, v)):
+ *    3 n^2/8 bytes per nonterminal (the relation, last round's new facts,
+ *    this round's derived facts).  Bookkeeping only, so that a round costs
+ *    what its new facts cost: the rows holding new facts are listed, and the
+ *    rows a round writes are flagged.  Rows of one composition are computed
+ *    in parallel on `threads` threads.  rounds (optional) receives the number
+ *    of rounds, the last (empty) one included.
  * Returns 0, -1 on bad input, -2 when memory runs out.
  */
-#define NOT_LISTED 0xFFFFFFFFu
-
 typedef struct {
     uint64_t *rel, *cur, *nxt;   /* n * W words each */
+    uint32_t *cur_rows;          /* rows of cur that hold a fact, cur_nrows of them */
+    uint32_t cur_nrows;
+    uint8_t *touched;            /* [n]: row of nxt written this round */
     uint64_t rel_count, cur_count;
 } relset;
 
-static uint64_t bits_count(const uint64_t *b, uint64_t words) {
-    uint64_t c = 0;
-    for (uint64_t i = 0; i < words; i++) c += (uint64_t)__builtin_popcountll(b[i]);
-    return c;
-}
-
-/* out |= X ; Y  (rows u of out: OR of rows Y[v] over v in X[u]).  When Y
- * holds few pairs its rows are walked as lists (built here), otherwise they
- * are OR-ed word by word; X[u] is first restricted to the v whose Y row is
- * non-empty. */
-static int compose_into(uint64_t *out, const uint64_t *X, const uint64_t *Y, uint64_t y_count, uint32_t n,
-                        uint64_t W, int threads) {
+/* out |= X ; Y over the rows u in rows[0..nrows) (or all n rows if rows is
+ * NULL): out[u] = OR of Y[v] over v in X[u].  When Y holds few pairs its rows
+ * are walked as lists (built here), otherwise they are OR-ed word by word;
+ * X[u] is first restricted to the v whose Y row is non-empty. */
+static int compose_into(uint64_t *out, uint8_t *touched, const uint64_t *X, const uint32_t *rows, uint32_t nrows,
+                        const uint64_t *Y, uint64_t y_count, uint32_t n, uint64_t W, int threads) {
     uint64_t *ynz = (uint64_t *)calloc(W ? W : 1, sizeof(uint64_t));
     if (!ynz) return -2;
     for (uint32_t v = 0; v < n; v++) {
@@ -449,13 +446,17 @@ static int compose_into(uint64_t *out, const uint64_t *X, const uint64_t *Y, uin
         }
         yoff[n] = at;
     }
+    const int64_t count = rows ? (int64_t)nrows : (int64_t)n;
 #pragma omp parallel for num_threads(threads) schedule(dynamic, 64)
-    for (uint32_t u = 0; u < n; u++) {
+    for (int64_t i = 0; i < count; i++) {
+        const uint32_t u = rows ? rows[i] : (uint32_t)i;
         const uint64_t *xr = X + (uint64_t)u * W;
         uint64_t *orow = out + (uint64_t)u * W;
+        int wrote = 0;
         for (uint64_t k = 0; k < W; k++) {
             for (uint64_t b = xr[k] & ynz[k]; b; b &= b - 1) {
                 uint32_t v = (uint32_t)(k * 64 + __builtin_ctzll(b));
+                wrote = 1;
                 if (lists) {
                     for (uint64_t e = yoff[v]; e < yoff[v + 1]; e++) {
                         uint32_t w = ycol[e];
@@ -467,6 +468,7 @@ static int compose_into(uint64_t *out, const uint64_t *X, const uint64_t *Y, uin
                 }
             }
         }
+        if (wrote) touched[u] = 1;
     }
     free(yoff); free(ycol); free(ynz);
     return 0;
@@ -496,55 +498,82 @@ int oracle_cfl_rounds(uint32_t n, uint64_t m, const uint32_t *src, const uint32_
         R[a].rel = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
         R[a].cur = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
         R[a].nxt = (uint64_t *)calloc(words ? words : 1, sizeof(uint64_t));
-        if (!R[a].rel || !R[a].cur || !R[a].nxt) rc = -2;
+        R[a].cur_rows = (uint32_t *)malloc(((size_t)n ? n : 1) * sizeof(uint32_t));
+        R[a].touched = (uint8_t *)calloc((size_t)n ? n : 1, 1);
+        if (!R[a].rel || !R[a].cur || !R[a].nxt || !R[a].cur_rows || !R[a].touched) rc = -2;
     }
-    /* round 0: eps and terminal facts are all new */
+    /* round 0: eps and terminal facts, all of them new; they are gathered in
+     * nxt and enter like any round's derived facts */
     for (uint32_t r = 0; r < n_rules && !rc; r++) {
-        uint64_t *c = R[lhs[r]].cur;
+        relset *A = &R[lhs[r]];
         if (kind[r] == R_EPS)
-            for (uint32_t u = 0; u < n; u++) c[(uint64_t)u * W + (u >> 6)] |= 1ull << (u & 63);
+            for (uint32_t u = 0; u < n; u++) {
+                A->nxt[(uint64_t)u * W + (u >> 6)] |= 1ull << (u & 63);
+                A->touched[u] = 1;
+            }
         if (kind[r] == R_TERM)
             for (uint64_t i = 0; i < m; i++)
-                if (lbl[i] == x[r]) c[(uint64_t)src[i] * W + (dst[i] >> 6)] |= 1ull << (dst[i] & 63);
+                if (lbl[i] == x[r]) {
+                    A->nxt[(uint64_t)src[i] * W + (dst[i] >> 6)] |= 1ull << (dst[i] & 63);
+                    A->touched[src[i]] = 1;
+                }
     }
-    for (uint32_t a = 0; a < n_nt && !rc; a++) {
-        memcpy(R[a].rel, R[a].cur, words * sizeof(uint64_t));
-        R[a].cur_count = R[a].rel_count = bits_count(R[a].cur, words);
-    }
-    uint32_t nr = 1;
+    uint32_t nr = 0;
     for (;;) {
         if (rc) break;
+        /* merge: the derived facts not yet known are the new facts */
         int any_new = 0;
-        for (uint32_t a = 0; a < n_nt; a++) any_new |= R[a].cur_count != 0;
-        if (!any_new) break;
+        for (uint32_t a = 0; a < n_nt; a++) {
+            relset *A = &R[a];
+            /* last round's new-fact rows are cleared; nxt becomes the new cur */
+            for (uint32_t i = 0; i < A->cur_nrows; i++)
+                memset(A->cur + (uint64_t)A->cur_rows[i] * W, 0, W * sizeof(uint64_t));
+            uint32_t nrows = 0;
+            uint64_t c = 0;
+            for (uint32_t u = 0; u < n; u++) {
+                if (!A->touched[u]) continue;
+                A->touched[u] = 0;
+                uint64_t *nx = A->nxt + (uint64_t)u * W, *rl = A->rel + (uint64_t)u * W;
+                uint64_t cu = 0;
+                for (uint64_t k = 0; k < W; k++) {
+                    uint64_t nw = nx[k] & ~rl[k];
+                    nx[k] = nw;
+                    rl[k] |= nw;
+                    cu += (uint64_t)__builtin_popcountll(nw);
+                }
+                if (cu) A->cur_rows[nrows++] = u;
+                else memset(nx, 0, W * sizeof(uint64_t));
+                c += cu;
+            }
+            uint64_t *t = A->cur; A->cur = A->nxt; A->nxt = t;
+            A->cur_nrows = nrows;
+            A->cur_count = c;
+            A->rel_count += c;
+            any_new |= c != 0;
+        }
         nr++;
-        for (uint32_t a = 0; a < n_nt; a++) memset(R[a].nxt, 0, words * sizeof(uint64_t));
+        if (!any_new) break;
+        /* derive: every rule, reading rel and cur, writing nxt */
         for (uint32_t r = 0; r < n_rules && !rc; r++) {
             relset *A = &R[lhs[r]];
             if (kind[r] == R_UNIT) {
                 const relset *B = &R[x[r]];
-                if (!B->cur_count) continue;
-                for (uint64_t i = 0; i < words; i++) A->nxt[i] |= B->cur[i];
+                for (uint32_t i = 0; i < B->cur_nrows; i++) {
+                    const uint32_t u = B->cur_rows[i];
+                    const uint64_t *bs = B->cur + (uint64_t)u * W;
+                    uint64_t *ad = A->nxt + (uint64_t)u * W;
+                    for (uint64_t k = 0; k < W; k++) ad[k] |= bs[k];
+                    A->touched[u] = 1;
+                }
             } else if (kind[r] == R_BIN) {
                 const relset *B = &R[x[r]], *C = &R[y[r]];
                 /* new ; all  and  all ; new */
-                if (B->cur_count && C->rel_count) rc = compose_into(A->nxt, B->cur, C->rel, C->rel_count, n, W, threads);
+                if (B->cur_count && C->rel_count)
+                    rc = compose_into(A->nxt, A->touched, B->cur, B->cur_rows, B->cur_nrows, C->rel, C->rel_count, n,
+                                      W, threads);
                 if (!rc && B->rel_count && C->cur_count)
-                    rc = compose_into(A->nxt, B->rel, C->cur, C->cur_count, n, W, threads);
+                    rc = compose_into(A->nxt, A->touched, B->rel, NULL, 0, C->cur, C->cur_count, n, W, threads);
             }
-        }
-        for (uint32_t a = 0; a < n_nt && !rc; a++) {
-            relset *A = &R[a];
-            uint64_t c = 0;
-            for (uint64_t i = 0; i < words; i++) {
-                uint64_t nw = A->nxt[i] & ~A->rel[i];
-                A->nxt[i] = nw;
-                A->rel[i] |= nw;
-                c += (uint64_t)__builtin_popcountll(nw);
-            }
-            uint64_t *t = A->cur; A->cur = A->nxt; A->nxt = t;
-            A->cur_count = c;
-            A->rel_count += c;
         }
     }
     if (!rc) {
@@ -555,7 +584,9 @@ int oracle_cfl_rounds(uint32_t n, uint64_t m, const uint32_t *src, const uint32_
         }
         if (rounds) *rounds = nr;
     }
-    for (uint32_t a = 0; a < n_nt; a++) { free(R[a].rel); free(R[a].cur); free(R[a].nxt); }
+    for (uint32_t a = 0; a < n_nt; a++) {
+        free(R[a].rel); free(R[a].cur); free(R[a].nxt); free(R[a].cur_rows); free(R[a].touched);
+    }
     free(R);
     return rc;
 }
