@@ -138,7 +138,15 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                components of the product graph, each component's row
  *                computed once in topological order; only for RSMs without
  *                box-labelled transitions, i.e. regular queries, else
- *                CFPQ_ERR_INVALID).  AUTO picks FUSED for small graphs,
+ *                CFPQ_ERR_INVALID), _PEREDGE (the literal per-edge
+ *                incremental closure of Sec. 3.1.1: the closure of the whole
+ *                product graph kept as one bitset row per product node, every
+ *                new product edge (i, j) added on its own -- each node that
+ *                reaches i and not j takes in j's row and j -- in one
+ *                workgroup; needs states * n <= 65536, else CFPQ_ERR_LIMIT;
+ *                keep_rank and keep_blocks give CFPQ_ERR_INVALID; never
+ *                picked by AUTO: it is the comparison arm of the method's
+ *                complexity argument).  AUTO picks FUSED for small graphs,
  *                CONDENSED for other regular queries, LEVELS otherwise.
  *                A CONDENSED query on a graph that has run one before goes
  *                out in one piece, sized by the launch chains the previous
@@ -149,7 +157,10 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                fails with CFPQ_ERR_LIMIT if the loop has not stopped after
  *                max_iters iterations.
  *   keep_rank  : keep, for every nonterminal pair, the iteration that added
- *                it; required by cfpq_extract_path (n <= 16384).
+ *                it (one byte per pair of every box, on the device: boxes *
+ *                n^2 bytes, at most 64 GiB, else CFPQ_ERR_LIMIT); required by
+ *                cfpq_extract_path when the RSM has box-labelled
+ *                transitions.
  *   keep_blocks: keep the closure blocks, required by cfpq_result_block.
  *   tile_words : source-tile width in 64-bit words (levels strategy; the
  *                closure runs once per tile of sources).  0 = automatic:
@@ -195,7 +206,8 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  * Errors: CFPQ_ERR_INVALID if the RSM uses more terminals than the graph
  *   has labels; CFPQ_ERR_OOM; CFPQ_ERR_DEVICE; CFPQ_ERR_LIMIT.
  * ---------------------------------------------------------------------- */
-enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2, CFPQ_STRATEGY_CONDENSED = 3 };
+enum { CFPQ_STRATEGY_AUTO = 0, CFPQ_STRATEGY_LEVELS = 1, CFPQ_STRATEGY_FUSED = 2, CFPQ_STRATEGY_CONDENSED = 3,
+       CFPQ_STRATEGY_PEREDGE = 4 };
 enum { CFPQ_NT_AUTO = 0, CFPQ_NT_ROWS = 1, CFPQ_NT_MFMA = 2 };
 
 typedef struct {
@@ -291,7 +303,10 @@ cfpq_status cfpq_result_stats(cfpq_result res, uint32_t *iterations, uint64_t *d
 
 /* ------------------------------------------------------------------------
  * One witness path for (u, v) in box's relation (Sec. 3.2: a single path can
- * always be extracted).  Requires keep_rank.  edges receives 3 * n_edges
+ * always be extracted).  Requires keep_rank if the RSM has box-labelled
+ * transitions (a regular query needs no ranks).  The breadth-first search
+ * over the product graph runs on the device, one launch per level; the
+ * parent walk reads the parent entries back.  edges receives 3 * n_edges
  * uint32 values (src, label, dst) in path order; an empty path (u == v, box
  * nullable) has n_edges == 0.  Each nonterminal edge is expanded through
  * edges added in strictly earlier iterations, so the expansion terminates.
@@ -310,11 +325,12 @@ cfpq_status cfpq_extract_path(cfpq_result res, uint32_t box, uint32_t u, uint32_
  * as cfpq_paths_next asks for them.  The empty path is included when
  * u == v and box derives the empty word.
  *
- * cfpq_paths_open: requires a result kept with keep_rank (n <= 16384); the
- * iterator copies what it needs, so res may be destroyed afterwards.  If
+ * cfpq_paths_open: any result (ranks are not needed: membership of (u, v)
+ * is read from the returned relation); the iterator shares the graph's host
+ * edge lists and copies the RSM, so res may be destroyed afterwards.  If
  * (u, v) is not in box's relation (as returned, vertex masks included) the
  * iterator is empty.  Errors: CFPQ_ERR_INVALID (NULL arguments, box or
- * vertex out of range, no ranks kept).
+ * vertex out of range, max_edges above 4096).
  * cfpq_paths_next: the next path into edges (3 uint32 per edge: src, label,
  * dst).  CFPQ_ERR_NOT_FOUND when no path is left; CFPQ_ERR_BUFFER with
  * *n_edges set if cap_edges is too small (the path is kept for the next

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfpq.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("api.hip", "kernels.hip", "condense.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("api.hip", "kernels.hip", "condense.hip", "peredge.hip")]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 FLAGS = [

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libcfpq.so")
 OK, ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_NOT_FOUND, ERR_BUFFER, ERR_LIMIT, ERR_REJECTED = 0, -1, -2, -3, -4, -5, -6, -7
 ADD_INVERSES = 1
 DEVICE_PTRS = 2
-STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED, STRATEGY_CONDENSED = 0, 1, 2, 3
+STRATEGY_AUTO, STRATEGY_LEVELS, STRATEGY_FUSED, STRATEGY_CONDENSED, STRATEGY_PEREDGE = 0, 1, 2, 3, 4
 NT_AUTO, NT_ROWS, NT_MFMA = 0, 1, 2
 
 _STATUS = {0: "OK", -1: "INVALID", -2: "OOM", -3: "DEVICE", -4: "NOT_FOUND", -5: "BUFFER", -6: "LIMIT",

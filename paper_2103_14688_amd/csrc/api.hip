@@ -106,6 +106,12 @@ struct DevBuf {
 
 uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 
+// the graph's successor lists on the host, shared by the graph and the
+// results made on it (path extraction reads them after the graph is gone)
+struct HostCsr {
+    std::vector<uint32_t> off, out;   // label l, vertex u: out[off[l * (n + 1) + u] .. off[l * (n + 1) + u + 1]), sorted
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -118,7 +124,7 @@ struct cfpq_graph_s {
     Alloc alloc;
     DevBuf off, idx;                         // CSC per label (predecessors)
     DevBuf soff, sidx;                       // CSR per label (successors)
-    std::vector<uint32_t> h_out_off, h_out;  // CSR per label (successors), host
+    std::shared_ptr<HostCsr> hcsr;           // CSR per label (successors), host
     // launch-chain sizes the last condensed query on this graph needed; with
     // all three set, the next condensed query goes out in one piece with
     // these sizes (speculation only: a chain that needs more continues on
@@ -146,14 +152,26 @@ struct cfpq_result_s {
     std::vector<uint64_t> deltas;
     double ms = 0.0;
     cfpq_rsm_s rsm;                              // copy
-    std::vector<uint32_t> out_off, out;          // graph successors (keep_rank only)
+    std::shared_ptr<const HostCsr> hcsr;         // graph successors (the graph's, shared)
     uint32_t n_labels = 0;
-    std::vector<uint8_t> h_rank;                 // lazily fetched, [N][u][v]
+    struct WitnessDev;
+    std::unique_ptr<WitnessDev> wdev;            // witness search buffers, built on first use
     struct Prof {
         uint64_t launches = 0, bytes = 0;
         double ms = 0.0;
     } prof[9];
     bool profiled = false;
+};
+
+// buffers of the device witness search, kept by the result after the first
+// extraction: the graph's successor lists, the RSM's transitions by source
+// state and its final states, parent pointers and two frontiers
+struct cfpq_result_s::WitnessDev {
+    DevBuf buf;
+    uint32_t *off = nullptr, *idx = nullptr, *s_off = nullptr, *fin = nullptr, *par = nullptr, *psym = nullptr;
+    uint32_t *fr[2] = {nullptr, nullptr};
+    InTrans *s_tr = nullptr;
+    unsigned int *ctr = nullptr;
 };
 
 // ---------------------------------------------------------------------------
@@ -227,20 +245,21 @@ extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const ui
     const uint64_t noff = (uint64_t)L * (n + 1);
     std::vector<uint32_t> off(noff, 0), idx(e.size());
     try {
-        g->h_out_off.assign(noff, 0);
-        g->h_out.resize(e.size());
+        g->hcsr = std::make_shared<HostCsr>();
+        g->hcsr->off.assign(noff, 0);
+        g->hcsr->out.resize(e.size());
     } catch (...) {
         return fail(CFPQ_ERR_OOM, "host allocation failed");
     }
     for (const E &x : e) {
         off[(uint64_t)x.l * (n + 1) + x.d + 1]++;
-        g->h_out_off[(uint64_t)x.l * (n + 1) + x.s + 1]++;
+        g->hcsr->off[(uint64_t)x.l * (n + 1) + x.s + 1]++;
     }
     // offsets are global across labels: label l's lists start where l-1's end
     uint64_t run = 0, run2 = 0;
     for (uint32_t l = 0; l < L; ++l) {
         uint32_t *o = &off[(uint64_t)l * (n + 1)];
-        uint32_t *o2 = &g->h_out_off[(uint64_t)l * (n + 1)];
+        uint32_t *o2 = &g->hcsr->off[(uint64_t)l * (n + 1)];
         o[0] = (uint32_t)run;
         o2[0] = (uint32_t)run2;
         for (uint32_t v = 0; v < n; ++v) {
@@ -252,12 +271,12 @@ extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const ui
     }
     for (uint64_t i = 0; i < e.size(); ++i) idx[i] = e[i].s;  // sorted by (l, d, s)
     {
-        std::vector<uint32_t> fill(g->h_out_off.begin(), g->h_out_off.end());
-        for (const E &x : e) g->h_out[fill[(uint64_t)x.l * (n + 1) + x.s]++] = x.d;
+        std::vector<uint32_t> fill(g->hcsr->off.begin(), g->hcsr->off.end());
+        for (const E &x : e) g->hcsr->out[fill[(uint64_t)x.l * (n + 1) + x.s]++] = x.d;
         for (uint32_t l = 0; l < L; ++l)
             for (uint32_t u = 0; u < n; ++u) {
-                uint64_t a = g->h_out_off[(uint64_t)l * (n + 1) + u], b = g->h_out_off[(uint64_t)l * (n + 1) + u + 1];
-                std::sort(g->h_out.begin() + a, g->h_out.begin() + b);
+                uint64_t a = g->hcsr->off[(uint64_t)l * (n + 1) + u], b = g->hcsr->off[(uint64_t)l * (n + 1) + u + 1];
+                std::sort(g->hcsr->out.begin() + a, g->hcsr->out.begin() + b);
             }
     }
     if (!g->off.alloc(&g->alloc, noff * sizeof(uint32_t), s) ||
@@ -266,10 +285,10 @@ extern "C" cfpq_status cfpq_graph_create(uint32_t n, uint32_t n_labels, const ui
         !g->sidx.alloc(&g->alloc, idx.size() * sizeof(uint32_t), s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (graph)");
     HIP_TRY(hipMemcpyAsync(g->off.p, off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(g->soff.p, g->h_out_off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->soff.p, g->hcsr->off.data(), noff * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     if (!idx.empty()) {
         HIP_TRY(hipMemcpyAsync(g->idx.p, idx.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemcpyAsync(g->sidx.p, g->h_out.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(g->sidx.p, g->hcsr->out.data(), idx.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     *out = g.release();
@@ -341,6 +360,7 @@ namespace {
 constexpr uint32_t kFusedMaxN = 2048;
 constexpr uint32_t kFusedMaxBoxesHost = 64;
 constexpr uint32_t kStatsCap = 4096;
+constexpr uint64_t kRankMaxBytes = 64ull << 30;   // keep_rank: one byte per pair of every box
 
 struct Plan {
     uint32_t n, Pn, P, nQ, nB, n_terms;
@@ -1463,6 +1483,82 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
 }
 
 // ---------------------------------------------------------------------------
+// PEREDGE strategy: the literal per-edge incremental closure (small graphs)
+// ---------------------------------------------------------------------------
+constexpr uint64_t kPerEdgeMaxNodes = 65536;          // product nodes nQ * n
+constexpr uint64_t kPerEdgeMaxClosureBytes = 512ull << 20;
+
+bool peredge_ok(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
+    const uint64_t N = (uint64_t)r.n_states * g.n, W = (N + 63) / 64;
+    return N <= kPerEdgeMaxNodes && N * W * 8 <= kPerEdgeMaxClosureBytes;
+}
+
+cfpq_status run_peredge(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o, cfpq_result_s &res) {
+    hipStream_t s = (hipStream_t)o.stream;
+    const Alloc *al = &res.alloc;
+    Plan p = make_plan(g, r);
+    Tables tb;
+    cfpq_status st = upload_tables(p, al, s, tb);
+    if (st != CFPQ_OK) return st;
+    const uint32_t n = p.n, nQ = p.nQ, nB = p.nB;
+    const uint64_t N = (uint64_t)nQ * n, W = (N + 63) / 64, Wn = p.Pn;
+    // transitions as three arrays, in the RSM's order
+    std::vector<uint32_t> tr(3 * r.t_src.size());
+    for (size_t i = 0; i < r.t_src.size(); ++i) {
+        tr[i] = r.t_src[i];
+        tr[r.t_src.size() + i] = r.t_sym[i];
+        tr[2 * r.t_src.size() + i] = r.t_dst[i];
+    }
+    DevBuf C, M, dM, trb, stats;
+    const uint64_t mw = (uint64_t)nB * n * Wn;
+    if (!C.alloc(al, N * W * 8, s) || !M.alloc(al, mw * 8, s) || !dM.alloc(al, mw * 8, s) ||
+        !trb.alloc(al, tr.size() * 4 + 16, s) || !stats.alloc(al, (3 + kStatsCap) * 8, s) ||
+        !res.NT.alloc(al, (uint64_t)nB * n * p.P * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (per-edge closure)");
+    if (!tr.empty()) HIP_TRY(hipMemcpyAsync(trb.p, tr.data(), tr.size() * 4, hipMemcpyHostToDevice, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    struct EvGuard {
+        hipEvent_t *a, *b;
+        ~EvGuard() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } evg{&e0, &e1};
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(launch_fill(C.as<uint64_t>(), N * W, 0, s));
+    HIP_TRY(launch_fill(M.as<uint64_t>(), mw, 0, s));
+    HIP_TRY(launch_fill(dM.as<uint64_t>(), mw, 0, s));
+    PerEdgeQuery q{};
+    q.n = n; q.nQ = nQ; q.nB = nB; q.n_terms = p.n_terms; q.n_trans = (uint32_t)r.t_src.size();
+    q.N = (uint32_t)N; q.W = (uint32_t)W; q.Wn = (uint32_t)Wn;
+    q.soff = g.soff.as<uint32_t>(); q.sidx = g.sidx.as<uint32_t>();
+    q.t_src = trb.as<uint32_t>(); q.t_sym = q.t_src + r.t_src.size(); q.t_dst = q.t_sym + r.t_src.size();
+    q.starts = tb.starts; q.fin_off = tb.fin_off; q.fin = tb.fin; q.nullable = tb.nullable;
+    q.C = C.as<uint64_t>(); q.M = M.as<uint64_t>(); q.dM = dM.as<uint64_t>();
+    q.stats = stats.as<unsigned long long>();
+    q.max_iters = o.max_iters; q.stats_cap = kStatsCap;
+    HIP_TRY(launch_peredge(q, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    // result layout: row v of box N holds the sources u (transposed rows)
+    HIP_TRY(launch_fill(res.NT.as<uint64_t>(), (uint64_t)nB * n * p.P, 0, s));
+    for (uint32_t b = 0; b < nB; ++b)
+        HIP_TRY(launch_transpose(M.as<uint64_t>() + (uint64_t)b * n * Wn, (uint32_t)Wn,
+                                 res.NT.as<uint64_t>() + (uint64_t)b * n * p.P, p.P, n, s));
+    std::vector<unsigned long long> h(3 + kStatsCap);
+    HIP_TRY(hipMemcpyAsync(h.data(), stats.p, h.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    res.ms = ms;
+    res.iterations = (uint32_t)h[0];
+    res.deltas.assign(h.begin() + 3, h.begin() + 3 + std::min<uint64_t>(h[0], kStatsCap));
+    return CFPQ_OK;
+}
+
+// ---------------------------------------------------------------------------
 // FUSED strategy: a workgroup per query, many queries per launch
 // ---------------------------------------------------------------------------
 struct FusedJob {
@@ -1587,10 +1683,7 @@ cfpq_result_s *new_result(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     res->alloc = Alloc(o.alloc);
     res->rsm = r;
     res->n_labels = g.n_labels;
-    if (o.keep_rank) {
-        res->out_off = g.h_out_off;
-        res->out = g.h_out;
-    }
+    res->hcsr = g.hcsr;
     return res;
 }
 
@@ -1601,11 +1694,18 @@ bool has_calls(const cfpq_rsm_s &r) {
 }
 
 cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
-    if (o.strategy > CFPQ_STRATEGY_CONDENSED) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.strategy > CFPQ_STRATEGY_PEREDGE) return fail(CFPQ_ERR_INVALID, "unknown strategy");
+    if (o.strategy == CFPQ_STRATEGY_PEREDGE) {
+        if (o.keep_rank || o.keep_blocks)
+            return fail(CFPQ_ERR_INVALID, "per-edge strategy keeps neither ranks nor closure blocks");
+        if (!peredge_ok(g, r))
+            return fail(CFPQ_ERR_LIMIT, "per-edge strategy needs states * n <= 65536 (the whole product closure)");
+    }
     if (o.nt_mode > CFPQ_NT_MFMA) return fail(CFPQ_ERR_INVALID, "unknown nt_mode");
     if (o.strategy == CFPQ_STRATEGY_CONDENSED && has_calls(r))
         return fail(CFPQ_ERR_INVALID, "condensed strategy needs an RSM without box-labelled transitions");
-    if (o.keep_rank && g.n > 16384) return fail(CFPQ_ERR_LIMIT, "keep_rank needs n <= 16384");
+    if (o.keep_rank && (uint64_t)r.n_boxes * g.n * g.n > kRankMaxBytes)
+        return fail(CFPQ_ERR_LIMIT, "keep_rank: boxes * n^2 bytes of ranks exceed the 64 GiB limit");
     if (o.strategy == CFPQ_STRATEGY_FUSED && !fused_ok(g, r))
         return fail(CFPQ_ERR_LIMIT, "fused strategy needs n <= 2048 and at most 64 boxes");
     return CFPQ_OK;
@@ -1618,6 +1718,7 @@ bool use_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts
 }
 
 cfpq_status run_big(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o, cfpq_result_s &res) {
+    if (o.strategy == CFPQ_STRATEGY_PEREDGE) return run_peredge(g, r, o, res);
     const bool cond = o.strategy == CFPQ_STRATEGY_CONDENSED ||
                       (o.strategy == CFPQ_STRATEGY_AUTO && !has_calls(r) && (uint64_t)r.n_states * g.n < 0xFFFFFFFFull);
     return cond ? run_condensed(g, r, o, res) : run_levels(g, r, o, res);
@@ -1982,61 +2083,66 @@ struct Witness {
     std::vector<uint32_t> *out;
     uint64_t limit;
     bool overflow = false;
+    cfpq_status err = CFPQ_OK;
 
-    uint8_t rank(uint32_t N, uint32_t u, uint32_t v) const {
-        return r->h_rank[((uint64_t)N * r->n + u) * r->n + v];
+    uint8_t rank(uint32_t N, uint32_t u, uint32_t v) {
+        uint8_t b = 0xFF;
+        if (hipMemcpy(&b, r->rank.as<uint8_t>() + ((uint64_t)N * r->n + u) * r->n + v, 1, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            err = fail(CFPQ_ERR_DEVICE, "rank read failed");
+        return b;
     }
 
-    // product-graph BFS inside box N from (start, u) to (final, v) using
-    // terminal edges and nonterminal edges of rank < rk; expands the path.
+    // breadth-first search on the device inside box N from (start, u) to
+    // (final, v), over terminal edges and nonterminal edges of rank < rk;
+    // the path found is expanded (nonterminal edges recursively)
     bool expand(uint32_t N, uint32_t u, uint32_t v, uint8_t rk) {
-        if (overflow) return false;
+        if (overflow || err != CFPQ_OK) return false;
         if (rk == 0) return u == v;  // the epsilon loop: empty path
+        cfpq_result_s::WitnessDev &W = *r->wdev;
         const cfpq_rsm_s &R = r->rsm;
-        const uint32_t n = r->n, nQ = R.n_states;
-        const uint32_t start = R.box_start[N];
-        std::vector<uint32_t> states;
-        for (uint32_t q = 0; q < nQ; ++q)
-            if (R.state_box[q] == N) states.push_back(q);
-        // parent pointers over product nodes id = q * n + x
-        std::vector<int64_t> par((uint64_t)nQ * n, -1);
-        std::vector<uint32_t> par_sym((uint64_t)nQ * n, 0);
-        std::vector<uint32_t> queue;
-        const uint64_t s0 = (uint64_t)start * n + u;
-        par[s0] = (int64_t)s0;
-        queue.push_back((uint32_t)s0);
-        int64_t hit = -1;
-        for (size_t h = 0; h < queue.size() && hit < 0; ++h) {
-            const uint32_t node = queue[h];
-            const uint32_t q = node / n, x = node % n;
-            for (size_t t = 0; t < R.t_src.size() && hit < 0; ++t) {
-                if (R.t_src[t] != q) continue;
-                const uint32_t f = R.t_dst[t], sym = R.t_sym[t];
-                auto visit = [&](uint32_t y) {
-                    const uint64_t id = (uint64_t)f * n + y;
-                    if (par[id] >= 0) return;
-                    par[id] = node;
-                    par_sym[id] = sym;
-                    queue.push_back((uint32_t)id);
-                    if (y == v && R.is_final[f]) hit = (int64_t)id;
-                };
-                if (sym < R.n_terms) {
-                    const uint64_t a = r->out_off[(uint64_t)sym * (n + 1) + x], b = r->out_off[(uint64_t)sym * (n + 1) + x + 1];
-                    for (uint64_t e = a; e < b && hit < 0; ++e) visit(r->out[e]);
-                } else {
-                    const uint32_t M = sym - R.n_terms;
-                    for (uint32_t y = 0; y < n && hit < 0; ++y)
-                        if (rank(M, x, y) < rk) visit(y);
-                }
+        const uint32_t n = r->n;
+        const uint64_t nodes = (uint64_t)R.n_states * n;
+        hipStream_t s = r->stream;
+        const uint32_t s0 = R.box_start[N] * n + u;
+        if ((err = fill_start(W, nodes, s0, s)) != CFPQ_OK) return false;
+        WitnessBfs b{};
+        b.n = n; b.n_terms = R.n_terms; b.s_off = W.s_off; b.s_tr = W.s_tr; b.final = W.fin;
+        b.soff = W.off; b.sidx = W.idx; b.rank = r->rank.p ? r->rank.as<uint8_t>() : nullptr; b.rk = rk;
+        b.v_target = v; b.par = W.par; b.psym = W.psym; b.ctr = W.ctr;
+        uint32_t *cur = W.fr[0], *nxt = W.fr[1];
+        uint32_t ncur = 1, hit = kNoSlot;
+        while (ncur && hit == kNoSlot) {
+            b.cur = cur; b.ncur = ncur; b.next = nxt;
+            if (hipMemsetAsync(W.ctr, 0, 4, s) != hipSuccess || launch_witness_bfs(b, s) != hipSuccess) {
+                err = fail(CFPQ_ERR_DEVICE, "witness search launch failed");
+                return false;
             }
+            unsigned int c[2] = {0, 0};
+            if (hipMemcpyAsync(c, W.ctr, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+                err = fail(CFPQ_ERR_DEVICE, "witness search read failed");
+                return false;
+            }
+            ncur = c[0];
+            hit = c[1];
+            std::swap(cur, nxt);
         }
-        if (hit < 0) return false;
-        // walk back
+        if (hit == kNoSlot) return false;
+        // walk back along the parent pointers
         std::vector<std::array<uint32_t, 3>> steps;  // (x, sym, y)
-        for (uint64_t id = (uint64_t)hit; id != s0;) {
-            const uint64_t pid = (uint64_t)par[id];
-            steps.push_back({(uint32_t)(pid % n), par_sym[id], (uint32_t)(id % n)});
-            id = pid;
+        for (uint32_t id = hit; id != s0;) {
+            uint32_t ps[2];
+            if (hipMemcpy(&ps[0], W.par + id, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(&ps[1], W.psym + id, 4, hipMemcpyDeviceToHost) != hipSuccess) {
+                err = fail(CFPQ_ERR_DEVICE, "witness path read failed");
+                return false;
+            }
+            steps.push_back({ps[0] % n, ps[1], id % n});
+            id = ps[0];
+            if (steps.size() > nodes) {
+                err = fail(CFPQ_ERR_DEVICE, "internal error: parent pointers form a cycle");
+                return false;
+            }
         }
         std::reverse(steps.begin(), steps.end());
         for (auto &st : steps) {
@@ -2050,12 +2156,70 @@ struct Witness {
                 out->push_back(st[2]);
             } else {
                 const uint32_t M = st[1] - R.n_terms;
-                if (!expand(M, st[0], st[2], rank(M, st[0], st[2]))) return false;
+                const uint8_t rm = rank(M, st[0], st[2]);
+                if (err != CFPQ_OK || !expand(M, st[0], st[2], rm)) return false;
             }
         }
         return true;
     }
+
+    // no node reached yet except s0, which is its own parent and frontier 0
+    static cfpq_status fill_start(cfpq_result_s::WitnessDev &W, uint64_t nodes, uint32_t s0, hipStream_t s) {
+        HIP_TRY(launch_fill_u32(W.par, nodes, kNoSlot, s));
+        HIP_TRY(launch_fill_u32(W.par + s0, 1, s0, s));
+        HIP_TRY(launch_fill_u32(W.fr[0], 1, s0, s));
+        HIP_TRY(launch_fill_u32(W.ctr + 1, 1, kNoSlot, s));
+        return CFPQ_OK;
+    }
 };
+
+cfpq_status witness_setup(cfpq_result r) {
+    if (r->wdev) return CFPQ_OK;
+    const cfpq_rsm_s &R = r->rsm;
+    const uint32_t n = r->n, nQ = R.n_states;
+    const uint64_t nodes = (uint64_t)nQ * n;
+    const HostCsr &H = *r->hcsr;
+    std::vector<uint32_t> s_off(nQ + 1, 0);
+    std::vector<InTrans> s_tr(R.t_src.size());
+    for (size_t i = 0; i < R.t_src.size(); ++i) s_off[R.t_src[i] + 1]++;
+    for (uint32_t q = 0; q < nQ; ++q) s_off[q + 1] += s_off[q];
+    std::vector<uint32_t> fill(s_off.begin(), s_off.end() - 1);
+    for (size_t i = 0; i < R.t_src.size(); ++i) s_tr[fill[R.t_src[i]]++] = InTrans{R.t_dst[i], R.t_sym[i]};
+    std::vector<uint32_t> fin(nQ);
+    for (uint32_t q = 0; q < nQ; ++q) fin[q] = R.is_final[q] ? 1u : 0u;
+    // layout (4-byte words): off, idx, s_off, s_tr (2 words each), fin, par, psym, fr0, fr1, ctr
+    const uint64_t w_off = H.off.size(), w_idx = H.out.size() + 1, w_soff = s_off.size(), w_str = 2 * s_tr.size() + 2,
+                   w_fin = fin.size(), w_node = nodes;
+    const uint64_t total = w_off + w_idx + w_soff + w_str + w_fin + 4 * w_node + 4;
+    auto W = std::make_unique<cfpq_result_s::WitnessDev>();
+    if (!W->buf.alloc(&r->alloc, total * 4, r->stream)) return fail(CFPQ_ERR_OOM, "device allocation failed (witness)");
+    uint32_t *b = W->buf.as<uint32_t>();
+    W->off = b; b += w_off;
+    W->idx = b; b += w_idx;
+    W->s_off = b; b += w_soff;
+    W->s_tr = reinterpret_cast<InTrans *>(b); b += w_str;
+    W->fin = b; b += w_fin;
+    W->par = b; b += w_node;
+    W->psym = b; b += w_node;
+    W->fr[0] = b; b += w_node;
+    W->fr[1] = b; b += w_node;
+    W->ctr = reinterpret_cast<unsigned int *>(b);
+    hipStream_t s = r->stream;
+    HIP_TRY(hipMemcpyAsync(W->off, H.off.data(), H.off.size() * 4, hipMemcpyHostToDevice, s));
+    if (!H.out.empty()) HIP_TRY(hipMemcpyAsync(W->idx, H.out.data(), H.out.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W->s_off, s_off.data(), s_off.size() * 4, hipMemcpyHostToDevice, s));
+    if (!s_tr.empty()) HIP_TRY(hipMemcpyAsync(W->s_tr, s_tr.data(), s_tr.size() * sizeof(InTrans), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W->fin, fin.data(), fin.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));   // the host vectors die with this frame
+    r->wdev = std::move(W);
+    return CFPQ_OK;
+}
+
+bool has_box_calls(const cfpq_rsm_s &R) {
+    for (uint32_t sym : R.t_sym)
+        if (sym >= R.n_terms) return true;
+    return false;
+}
 
 }  // namespace
 
@@ -2064,43 +2228,44 @@ extern "C" cfpq_status cfpq_extract_path(cfpq_result r, uint32_t box, uint32_t u
     cfpq_status st = check_box(r, box);
     if (st != CFPQ_OK) return st;
     if (!n_edges) return fail(CFPQ_ERR_INVALID, "n_edges is NULL");
-    if (!r->rank.p) return fail(CFPQ_ERR_INVALID, "ranks were not kept (keep_rank)");
+    const bool calls = has_box_calls(r->rsm);
+    if (calls && !r->rank.p) return fail(CFPQ_ERR_INVALID, "ranks were not kept (keep_rank)");
     if (u >= r->n || v >= r->n) return fail(CFPQ_ERR_INVALID, "vertex out of range");
-    if (r->iterations > 254) return fail(CFPQ_ERR_LIMIT, "more than 254 iterations: ranks saturated");
-    if (r->h_rank.empty()) {
-        const uint64_t n = r->n;
-        std::vector<uint8_t> t;
-        try {
-            t.resize((uint64_t)r->nB * n * n);
-            r->h_rank.resize(t.size());
-        } catch (...) {
-            return fail(CFPQ_ERR_OOM, "host allocation failed");
+    if (calls && r->iterations > 254) return fail(CFPQ_ERR_LIMIT, "more than 254 iterations: ranks saturated");
+    try {
+        {   // the relation as returned (a vertex mask may have removed the pair)
+            uint64_t word = 0;
+            HIP_TRY(hipMemcpy(&word, r->NT.as<uint64_t>() + ((uint64_t)box * r->n + v) * r->P + (u >> 6), 8,
+                              hipMemcpyDeviceToHost));
+            if (!((word >> (u & 63)) & 1ull)) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
         }
-        HIP_TRY(hipMemcpy(t.data(), r->rank.p, t.size(), hipMemcpyDeviceToHost));
-        // device layout [N][v][u] -> host [N][u][v]
-        for (uint64_t N = 0; N < r->nB; ++N)
-            for (uint64_t vv = 0; vv < n; ++vv)
-                for (uint64_t uu = 0; uu < n; ++uu) r->h_rank[(N * n + uu) * n + vv] = t[(N * n + vv) * n + uu];
-    }
-    const uint8_t rk = r->h_rank[((uint64_t)box * r->n + u) * r->n + v];
-    if (rk == 0xFF) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
-    {   // the relation as returned (a vertex mask may have removed the pair)
-        uint64_t word = 0;
-        HIP_TRY(hipMemcpy(&word, r->NT.as<uint64_t>() + ((uint64_t)box * r->n + v) * r->P + (u >> 6), 8,
-                          hipMemcpyDeviceToHost));
-        if (!((word >> (u & 63)) & 1ull)) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
-    }
-    std::vector<uint32_t> out;
-    Witness w{r, &out, (uint64_t)1 << 26};
-    if (!w.expand(box, u, v, rk)) {
-        if (w.overflow) return fail(CFPQ_ERR_LIMIT, "witness longer than 2^26 edges");
-        return fail(CFPQ_ERR_DEVICE, "internal error: no witness through lower-rank edges");
-    }
-    *n_edges = out.size() / 3;
-    if (cap_edges < out.size() / 3) return fail(CFPQ_ERR_BUFFER, "edge buffer too small");
-    if (!out.empty()) {
-        if (!edges) return fail(CFPQ_ERR_INVALID, "edges is NULL");
-        std::memcpy(edges, out.data(), out.size() * 4);
+        if ((st = witness_setup(r)) != CFPQ_OK) return st;
+        std::vector<uint32_t> out;
+        Witness w{r, &out, (uint64_t)1 << 26};
+        // rank of the pair: the iteration that added it (0: the epsilon loop);
+        // a regular query has no ranks: a path of length >= 1, or the empty
+        // path where the box derives the empty word
+        uint8_t rk;
+        if (calls) {
+            rk = w.rank(box, u, v);
+            if (w.err != CFPQ_OK) return w.err;
+            if (rk == 0xFF) return fail(CFPQ_ERR_NOT_FOUND, "pair not in the relation");
+        } else {
+            rk = (u == v && r->rsm.is_final[r->rsm.box_start[box]]) ? 0 : 1;
+        }
+        if (!w.expand(box, u, v, rk)) {
+            if (w.err != CFPQ_OK) return w.err;
+            if (w.overflow) return fail(CFPQ_ERR_LIMIT, "witness longer than 2^26 edges");
+            return fail(CFPQ_ERR_DEVICE, "internal error: no witness through lower-rank edges");
+        }
+        *n_edges = out.size() / 3;
+        if (cap_edges < out.size() / 3) return fail(CFPQ_ERR_BUFFER, "edge buffer too small");
+        if (!out.empty()) {
+            if (!edges) return fail(CFPQ_ERR_INVALID, "edges is NULL");
+            std::memcpy(edges, out.data(), out.size() * 4);
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(CFPQ_ERR_OOM, "host allocation failed");
     }
     return CFPQ_OK;
 }
@@ -2123,7 +2288,7 @@ extern "C" void cfpq_result_destroy(cfpq_result r) { delete r; }
 // ---------------------------------------------------------------------------
 struct cfpq_paths_s {
     uint32_t n = 0, W = 0, nQ = 0, nT = 0;
-    std::vector<uint32_t> out_off, out;                             // successors per label (sorted)
+    std::shared_ptr<const HostCsr> csr;                             // successors per label (sorted)
     std::vector<std::vector<std::pair<uint32_t, uint32_t>>> bin;    // A+ -> B+ C+
     std::vector<std::vector<uint32_t>> unit;                        // U(A), A included
     std::vector<uint8_t> nullable;
@@ -2137,8 +2302,8 @@ struct cfpq_paths_s {
         return ((uint64_t)A * n + x) * (uint64_t)(max_edges + 1) + l;
     }
     bool has_edge(uint32_t x, uint32_t t, uint32_t y) const {
-        const uint32_t *b = out.data() + out_off[(uint64_t)t * (n + 1) + x];
-        const uint32_t *e = out.data() + out_off[(uint64_t)t * (n + 1) + x + 1];
+        const uint32_t *b = csr->out.data() + csr->off[(uint64_t)t * (n + 1) + x];
+        const uint32_t *e = csr->out.data() + csr->off[(uint64_t)t * (n + 1) + x + 1];
         return std::binary_search(b, e, y);
     }
     static bool test(const std::vector<uint64_t> &s, uint32_t y) { return (s[y >> 6] >> (y & 63)) & 1ull; }
@@ -2152,7 +2317,8 @@ struct cfpq_paths_s {
             if (B >= nQ) {   // T_t
                 if (l == 1) {
                     const uint32_t t = B - nQ;
-                    for (uint32_t e = out_off[(uint64_t)t * (n + 1) + x]; e < out_off[(uint64_t)t * (n + 1) + x + 1]; ++e)
+                    const std::vector<uint32_t> &off = csr->off, &out = csr->out;
+                    for (uint32_t e = off[(uint64_t)t * (n + 1) + x]; e < off[(uint64_t)t * (n + 1) + x + 1]; ++e)
                         s[out[e] >> 6] |= 1ull << (out[e] & 63);
                 }
                 continue;
@@ -2237,7 +2403,6 @@ extern "C" cfpq_status cfpq_paths_open(cfpq_result r, uint32_t box, uint32_t u, 
     *out = nullptr;
     cfpq_status st = check_box(r, box);
     if (st != CFPQ_OK) return st;
-    if (!r->rank.p) return fail(CFPQ_ERR_INVALID, "ranks were not kept (keep_rank)");
     if (u >= r->n || v >= r->n) return fail(CFPQ_ERR_INVALID, "vertex out of range");
     if (max_edges > 4096) return fail(CFPQ_ERR_INVALID, "max_edges above 4096");
     try {
@@ -2250,10 +2415,7 @@ extern "C" cfpq_status cfpq_paths_open(cfpq_result r, uint32_t box, uint32_t u, 
         it->u = u;
         it->v = v;
         it->max_edges = max_edges;
-        it->out_off = r->out_off;
-        it->out = r->out;
-        for (uint64_t i = 0; i + 1 < it->out_off.size(); ++i)
-            std::sort(it->out.begin() + it->out_off[i], it->out.begin() + it->out_off[i + 1]);
+        it->csr = r->hcsr;   // lists sorted at graph creation
         const uint32_t nA = it->nQ + it->nT;
         // nullable X_q: least fixpoint
         it->nullable.assign(nA, 0);

@@ -112,7 +112,7 @@ struct WritebackArgs {
     const uint32_t *fin_off, *fin; // final states per box
     const uint64_t *T;
     uint64_t *NT, *dNT, *dnt_act;  // dnt_act pre-cleared
-    uint8_t *rank;                 // optional [nB][n][n]: rank[N][v][u]
+    uint8_t *rank;                 // optional [nB][n][n]: rank[N][u][v] (source-major)
     uint32_t iter;
     unsigned long long *ctr;
     uint32_t slot_base;            // new edges of box N counted at slot_base + N
@@ -302,5 +302,47 @@ struct FusedQuery {
 };
 hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query,
                         hipStream_t s);
+
+// One level of a breadth-first search over the product graph of a box (a
+// frontier vector times the product's Boolean adjacency), recording parent
+// pointers: the step of single-witness extraction (Sec. 3.2).  Terminal
+// transitions follow graph edges; box-labelled transitions (M, x, y) are
+// usable only where rank[M][x][y] < rk (pairs found in earlier iterations;
+// no rank array: none usable).  Claims are exclusive (atomic on par), so
+// every node enters one frontier once; a claimed (final state, v_target)
+// node is reported in *hit.
+struct WitnessBfs {
+    uint32_t n, n_terms;
+    const uint32_t *s_off;         // [nQ + 1] transitions by source state
+    const InTrans *s_tr;           // .src = target state, .sym
+    const uint32_t *final;         // [nQ] nonzero: final state
+    const uint32_t *soff, *sidx;   // graph successors per label
+    const uint8_t *rank;           // [nB][n][n] source-major, or null
+    uint32_t rk;
+    uint32_t v_target;
+    const uint32_t *cur;           // frontier node ids (q * n + x)
+    uint32_t ncur;
+    uint32_t *next;                // next frontier; its size in ctr[0]
+    uint32_t *par, *psym;          // per product node: parent node (kNoSlot = none), symbol
+    unsigned int *ctr;             // [0] next size, [1] hit node (kNoSlot = none)
+};
+hipError_t launch_witness_bfs(const WitnessBfs &b, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s);
+
+// Literal per-edge incremental closure (peredge.hip): the whole product
+// graph's closure, one new edge at a time, in one workgroup.
+struct PerEdgeQuery {
+    uint32_t n, nQ, nB, n_terms, n_trans;
+    uint32_t N, W, Wn;              // product nodes nQ * n, words per closure row, words per M row
+    const uint32_t *soff, *sidx;    // graph successors per label
+    const uint32_t *t_src, *t_sym, *t_dst;   // RSM transitions
+    const uint32_t *starts, *fin_off, *fin;
+    const uint8_t *nullable;
+    uint64_t *C;                    // [N][W] closure rows (targets reachable by >= 1 edge)
+    uint64_t *M, *dM;               // [nB][n][Wn] M2^N and its new edges, rows u (bits v)
+    unsigned long long *stats;      // [0] iterations, [1] status, [2] rows grown, [3..] deltas
+    uint32_t max_iters, stats_cap;
+};
+hipError_t launch_peredge(const PerEdgeQuery &q, hipStream_t s);
 
 }  // namespace cfpq

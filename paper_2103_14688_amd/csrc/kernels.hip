@@ -963,7 +963,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
                 while (bits) {
                     const int b = __ffsll((unsigned long long)bits) - 1;
                     bits &= bits - 1;
-                    a.rank[((uint64_t)N * a.n + v) * a.n + (uint64_t)k * 64 + b] = (uint8_t)(a.iter > 255 ? 255 : a.iter);
+                    a.rank[((uint64_t)N * a.n + (uint64_t)k * 64 + b) * a.n + v] = (uint8_t)(a.iter > 255 ? 255 : a.iter);
                 }
             }
         }
@@ -1108,6 +1108,54 @@ hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned lon
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// witness search: one breadth-first level over a box's product graph
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void bfs_claim(const WitnessBfs &b, uint32_t id, uint32_t from, uint32_t sym) {
+    if (atomicCAS(&b.par[id], kNoSlot, from) != kNoSlot) return;   // already reached
+    b.psym[id] = sym;
+    b.next[atomicAdd(&b.ctr[0], 1u)] = id;
+    if (id % b.n == b.v_target && b.final[id / b.n]) atomicCAS(&b.ctr[1], kNoSlot, id);
+}
+
+__global__ __launch_bounds__(kBlock) void k_witness_bfs(WitnessBfs b) {
+    const int lane = __lane_id();
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t i = wave; i < b.ncur; i += nwaves) {
+        const uint32_t node = b.cur[i], q = node / b.n, x = node % b.n;
+        for (uint32_t t = b.s_off[q]; t < b.s_off[q + 1]; ++t) {
+            const InTrans tr = b.s_tr[t];
+            const uint32_t f = tr.src;
+            if (tr.sym < b.n_terms) {
+                const uint32_t e0 = b.soff[(uint64_t)tr.sym * (b.n + 1) + x], e1 = b.soff[(uint64_t)tr.sym * (b.n + 1) + x + 1];
+                for (uint32_t e = e0 + (uint32_t)lane; e < e1; e += kWave) bfs_claim(b, f * b.n + b.sidx[e], node, tr.sym);
+            } else if (b.rank) {
+                const uint8_t *row = b.rank + ((uint64_t)(tr.sym - b.n_terms) * b.n + x) * b.n;
+                for (uint32_t y = (uint32_t)lane; y < b.n; y += kWave)
+                    if (row[y] < b.rk) bfs_claim(b, f * b.n + y, node, tr.sym);
+            }
+        }
+    }
+}
+
+hipError_t launch_witness_bfs(const WitnessBfs &b, hipStream_t s) {
+    if (!b.ncur) return hipSuccess;
+    hipLaunchKernelGGL(k_witness_bfs, dim3(grid_for((uint64_t)b.ncur * kWave)), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t value) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t value, hipStream_t s) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, value);
+    return hipGetLastError();
+}
+
 // 64x64 bit-block transpose, one wavefront per block: lane i holds source
 // row (64*vb + i), word ub; ballot of bit j across lanes is destination row
 // (64*ub + j), word vb.
@@ -1228,7 +1276,7 @@ __device__ bool writeback_row_thread(const WritebackArgs &a, uint32_t N, uint32_
             cnt_box += (unsigned long long)__popcll(nw);
             if (a.rank)
                 for (uint64_t bits = nw; bits; bits &= bits - 1)
-                    a.rank[((uint64_t)N * a.n + v) * a.n + (uint64_t)k * 64 + __builtin_ctzll(bits)] =
+                    a.rank[((uint64_t)N * a.n + (uint64_t)k * 64 + __builtin_ctzll(bits)) * a.n + v] =
                         (uint8_t)(a.iter > 255 ? 255 : a.iter);
         }
         dnt[k] = nw;

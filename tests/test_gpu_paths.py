@@ -182,15 +182,12 @@ def test_masked_pair_has_no_paths_and_buffer_protocol():
         cfpq.cfpq_paths_close(it)
 
 
-def test_paths_need_ranks_and_valid_arguments():
+def test_paths_without_ranks_and_valid_arguments():
     g = synth.make_graph(3, [(0, "a", 1)], ["a"])
     graph = cfpq.Graph.from_synth(g)
     q = cfpq.Query(rsm_mod.from_regex("a", g.labels))
-    res = cfpq.query(graph, q)
-    with pytest.raises(cfpq.CfpqError) as e:
-        cfpq.cfpq_paths_open(res.h, 0, 0, 1, 3)
-    assert e.value.status == cfpq.ERR_INVALID
-    res = cfpq.query(graph, q, keep_rank=True)
+    res = cfpq.query(graph, q)          # no ranks: all paths need only the index
+    assert library_paths(res, 0, 1, 3) == [((0, 0, 1),)]
     for args in [(1, 0, 1, 3), (0, 3, 1, 3), (0, 0, 9, 3)]:
         with pytest.raises(cfpq.CfpqError) as e:
             cfpq.cfpq_paths_open(res.h, *args)
@@ -207,3 +204,82 @@ def test_larger_graph_paths_sampled():
     pairs = [(int(u), int(v)) for u, v in res.pairs(0)[:: max(1, len(res.pairs(0)) // 12)].tolist()]
     n = check_all_pairs(g, lambda w: brute.bnf_accepts(prods, "S", w), res, 6, pairs=pairs)
     assert n >= len(pairs)
+
+
+# ---------------------------------------------------------------------------
+# witnesses and bounded paths at the workloads' sizes (validity checks: the
+# edges exist and join up, the word is in the language)
+# ---------------------------------------------------------------------------
+def _valid(path, u, v, edges, accepts, labels):
+    if len(path) == 0:
+        return u == v
+    assert path[0][0] == u and path[-1][2] == v
+    for (a, _, b), (c, _, d) in zip(path, path[1:]):
+        assert b == c
+    assert all((int(x), int(lb), int(y)) in edges for x, lb, y in path)
+    return accepts(tuple(labels[int(lb)] for _, lb, _ in path))
+
+
+def test_rpq_witnesses_and_paths_at_bench_size():
+    print("paths: RPQ witnesses and paths, power-law n=100000, no ranks kept", flush=True)
+    g = synth.powerlaw(100000, seed=synth.BASE_SEED + 2)
+    R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
+    graph, q = cfpq.Graph.from_synth(g), cfpq.Query(R)
+    res = cfpq.query(graph, q)
+    edges = set(zip(g.src.tolist(), g.lbl.tolist(), g.dst.tolist()))
+    pat = re.compile("(a|b)*cd*")
+    accepts = lambda w: pat.fullmatch("".join(w)) is not None
+    bm = res.bitmap(0)
+    rng = np.random.default_rng(91)
+    checked = 0
+    for u in rng.choice(g.n, size=12, replace=False).tolist():
+        row = np.unpackbits(bm[u].view(np.uint8), bitorder="little")[:g.n]
+        vs = np.flatnonzero(row)
+        if not len(vs):
+            continue
+        for v in rng.choice(vs, size=min(3, len(vs)), replace=False).tolist():
+            path = res.extract_path(u, v)
+            assert _valid(path, u, v, edges, accepts, g.labels)
+            # all paths of at most 4 edges: every one valid, shortest first,
+            # and the witness's length is the least one when it is within 4
+            ps = library_paths(res, u, v, 4)
+            assert all(_valid(np.asarray(p), u, v, edges, accepts, g.labels) for p in ps if p)
+            if len(path) <= 4:
+                assert ps and len(ps[0]) <= len(path)
+            checked += 1
+    assert checked >= 10
+    # a pair outside the relation
+    u = int(np.flatnonzero(bm.sum(axis=1) == 0)[0]) if (bm.sum(axis=1) == 0).any() else None
+    if u is not None:
+        with pytest.raises(cfpq.CfpqError) as e:
+            res.extract_path(u, (u + 1) % g.n)
+        assert e.value.status == cfpq.ERR_NOT_FOUND
+
+
+def test_grammar_witnesses_and_paths_at_samegen_size():
+    print("paths: same-generation witnesses and paths, hierarchy n=50000, ranks kept on the device", flush=True)
+    g, _ = synth.hierarchy(50000, seed=synth.BASE_SEED + 3)
+    prods = [("S", ["sc_r", "S", "sc"]), ("S", ["type_r", "S", "type"]), ("S", ["sc_r", "sc"]),
+             ("S", ["type_r", "type"])]
+    R = rsm_mod.from_grammar(synth.SAME_GEN_G1, g.labels)
+    res = cfpq.query(cfpq.Graph.from_synth(g), cfpq.Query(R), keep_rank=True)
+    edges = set(zip(g.src.tolist(), g.lbl.tolist(), g.dst.tolist()))
+    accepts = lambda w: brute.bnf_accepts(prods, "S", w)
+    rng = np.random.default_rng(92)
+    bm = res.bitmap(0)
+    rows = np.flatnonzero(bm.any(axis=1))
+    checked = 0
+    for u in rng.choice(rows, size=10, replace=False).tolist():
+        vs = np.flatnonzero(np.unpackbits(bm[u].view(np.uint8), bitorder="little")[:g.n])
+        for v in rng.choice(vs, size=min(2, len(vs)), replace=False).tolist():
+            path = res.extract_path(u, v)
+            assert _valid(path, u, v, edges, accepts, g.labels)
+            # bounded paths: the iterator memoises one n-bit set per
+            # (symbol, vertex, length) it visits, so the bound is kept short here
+            L = min(8, len(path) + 2)
+            ps = library_paths(res, u, v, L)
+            assert all(_valid(np.asarray(p), u, v, edges, accepts, g.labels) for p in ps)
+            if len(path) <= L:
+                assert ps and len(ps[0]) <= len(path)
+            checked += 1
+    assert checked >= 10
