@@ -1097,7 +1097,14 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     const bool nullable = !p.eps_boxes.empty();
     auto al256 = [](uint64_t x) { return (x + 255) / 256 * 256; };
     const uint64_t o_u32 = al256(((uint64_t)2 * kCtr + 8) * 8);
-    const uint64_t o_fnz = o_u32 + al256(Nu * 4 * (9 + kStripes) + 64);
+    // condensation links (kCondLinks per node in each direction, with
+    // counts) when the stripe indices fit in 32 bits
+#ifndef CFPQ_COND_LINKS
+#define CFPQ_COND_LINKS 1
+#endif
+    const bool links = CFPQ_COND_LINKS && (uint64_t)N * kStripes < (1ull << 32);
+    const uint64_t link_u32 = links ? (2 + 2 * (uint64_t)kCondLinks) * Nu : 0;
+    const uint64_t o_fnz = o_u32 + al256(Nu * 4 * (9 + kStripes) + link_u32 * 4 + 64);
     const uint64_t o_alive = o_fnz + al256(N64 + nzb + 64);
     const uint64_t o_act = o_alive + al256(N64);
     const uint64_t o_dnt = o_act + al256((uint64_t)nB * Pn * 8);
@@ -1122,6 +1129,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     pg.soff = g.soff.as<uint32_t>(); pg.sidx = g.sidx.as<uint32_t>();
     pg.in_off = tb.in_off; pg.in_tr = tb.in_tr; pg.out_off = tb.out_off; pg.out_tr = tb.out_tr;
     pg.src_mask = res.src_mask.as<uint64_t>();
+    if (links) {
+        pg.xin_cnt = stripe + (uint64_t)kStripes * Nu;
+        pg.xout_cnt = pg.xin_cnt + Nu;
+        pg.xin = pg.xout_cnt + Nu;
+        pg.xout = pg.xin + (uint64_t)kCondLinks * Nu;
+    }
 
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     struct EvGuard {

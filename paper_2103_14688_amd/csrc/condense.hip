@@ -411,6 +411,22 @@ __global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, u
         // in-edges from other components, four per step (independent loads)
         uint32_t k = 0;
         const uint32_t q = p / g.n, v = p - q * g.n;
+        // links: the distinct components p is entered from, and for every
+        // entering edge x -> p the stripe it retires in x's list
+        uint32_t lst[kCondLinks];
+        uint32_t nl = 0;
+        const uint32_t si = c * kStripes + p % kStripes;   // fits: N * kStripes < 2^32 when links are kept
+        auto link = [&](uint32_t x, uint32_t cx) {
+            if (!g.xin_cnt || cx == c) return;
+            bool seen = false;
+            for (uint32_t r = 0; r < nl && r < kCondLinks; ++r) seen |= lst[r] == cx;
+            if (!seen) {
+                if (nl < kCondLinks) lst[nl] = cx;
+                ++nl;
+            }
+            const uint32_t slot = atomicAdd(&g.xout_cnt[x], 1u);
+            if (slot < kCondLinks) g.xout[(uint64_t)x * kCondLinks + slot] = si;
+        };
         for (uint32_t t = g.in_off[q]; t < g.in_off[q + 1]; ++t) {
             const InTrans tr = g.in_tr[t];
             const uint32_t *o = g.goff + (uint64_t)tr.sym * (g.n + 1) + v;
@@ -419,11 +435,24 @@ __global__ void k_cond_count(ProdGraph g, const uint32_t *scc, uint32_t *size, u
             for (; i + 4 <= e; i += 4) {
                 const uint32_t x0 = base + g.gidx[i], x1 = base + g.gidx[i + 1], x2 = base + g.gidx[i + 2],
                                x3 = base + g.gidx[i + 3];
-                k += (scc[x0] != c) + (scc[x1] != c) + (scc[x2] != c) + (scc[x3] != c);
+                const uint32_t c0 = scc[x0], c1 = scc[x1], c2 = scc[x2], c3 = scc[x3];
+                k += (c0 != c) + (c1 != c) + (c2 != c) + (c3 != c);
+                link(x0, c0);
+                link(x1, c1);
+                link(x2, c2);
+                link(x3, c3);
             }
-            for (; i < e; ++i) k += scc[base + g.gidx[i]] != c;
+            for (; i < e; ++i) {
+                const uint32_t x = base + g.gidx[i], cx = scc[x];
+                k += cx != c;
+                link(x, cx);
+            }
         }
         if (k) atomicAdd(&stripe[(uint64_t)c * kStripes + p % kStripes], k);
+        if (g.xin_cnt) {
+            g.xin_cnt[p] = nl <= kCondLinks ? nl : kCondLinks + 1;
+            for (uint32_t r = 0; r < nl && r < kCondLinks; ++r) g.xin[(uint64_t)p * kCondLinks + r] = lst[r];
+        }
     }
 }
 
@@ -568,6 +597,48 @@ __device__ __forceinline__ void store_row_word(uint64_t *dst, uint64_t x) {
 #else
     *dst = x;
 #endif
+}
+
+// Row-phase word layout: lane l's kk-th word of a chunk is word kk * 64 + l
+// with 8-byte accesses, and words 2 (kk/2 * 64 + l) + {0, 1} (one 16-byte
+// access per pair) with CFPQ_COND_VEC = 2.
+constexpr int kCondVec = CFPQ_COND_VEC;
+typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t cond_word(int kk, int lane) {
+    return kCondVec == 1 ? (uint32_t)(kk * kWave + lane) : (uint32_t)(2 * ((kk >> 1) * kWave + lane));
+}
+// words w .. w + kCondVec - 1 of a chunk of cw words (zero past its end)
+__device__ __forceinline__ void load_words(const uint64_t *src, uint32_t w, uint32_t cw, uint64_t *x) {
+    if constexpr (kCondVec == 2) {
+        if (w + 1 < cw) {
+            const u64x2_t v = *reinterpret_cast<const u64x2_t *>(src + w);
+            x[0] = v.x;
+            x[1] = v.y;
+        } else {
+            x[0] = w < cw ? src[w] : 0ull;
+            x[1] = 0;
+        }
+    } else {
+        x[0] = w < cw ? src[w] : 0ull;
+    }
+}
+__device__ __forceinline__ void store_words(uint64_t *row, uint32_t w, uint32_t cw, const uint64_t *x) {
+    if constexpr (kCondVec == 2) {
+        if (w + 1 < cw) {
+            u64x2_t v;
+            v.x = x[0];
+            v.y = x[1];
+#if CFPQ_COND_NT
+            __builtin_nontemporal_store(v, reinterpret_cast<u64x2_t *>(row + w));
+#else
+            *reinterpret_cast<u64x2_t *>(row + w) = v;
+#endif
+        } else if (w < cw) {
+            store_row_word(row + w, x[0]);
+        }
+    } else if (w < cw) {
+        store_row_word(row + w, x[0]);
+    }
 }
 
 // word offset of component c's row: in R, or (bit 63 set) in the answer
@@ -760,12 +831,27 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
             tb = g.in_off[q];
             te = g.in_off[q + 1];
         }
-        // A. listed predecessor rows
+        // A. listed predecessor rows: from the node's links where it has
+        // them (no edge walk), else edge-parallel over its in-edges
         s_cnt[wib][lane] = 0;
-        const uint32_t ntr = wave_max_u32(te - tb);
+        bool walk_in = at;
+        if (g.xin_cnt && at) {
+            const uint32_t ic = g.xin_cnt[mine];
+            if (ic <= kCondLinks) {
+                walk_in = false;
+                uint32_t cnt = 0;
+                for (uint32_t r = 0; r < ic; ++r) {
+                    const uint32_t cx = g.xin[(uint64_t)mine * kCondLinks + r];
+                    if (nz[(uint64_t)cx * nch + ch]) s_pred[wib][lane][cnt++] = comp_off(cx, g.n, P, flags, multi);
+                }
+                s_cnt[wib][lane] = cnt;
+            }
+        }
+        static_assert(kCondLinks <= kCondPredCap, "linked predecessors fit the LDS list");
+        const uint32_t ntr = wave_max_u32(walk_in ? te - tb : 0u);
         for (uint32_t k = 0; k < ntr; ++k) {
             uint32_t b = 0, e = 0, sb = 0;
-            if (tb + k < te) {
+            if (walk_in && tb + k < te) {
                 const InTrans tr = g.in_tr[tb + k];
                 const uint32_t *o = g.goff + (uint64_t)tr.sym * (g.n + 1) + v;
                 b = o[0];
@@ -846,10 +932,8 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
 #pragma unroll
                 for (int q = 0; q < kNS; ++q)
 #pragma unroll
-                    for (int kk = 0; kk < kCondPassWords; ++kk) {
-                        const uint32_t w = (uint32_t)(kk * kWave + lane);
-                        x[q][kk] = w < cw ? src[q][w] : 0ull;
-                    }
+                    for (int kk = 0; kk < kCondPassWords; kk += kCondVec)
+                        load_words(src[q], cond_word(kk, lane), cw, &x[q][kk]);
 #pragma unroll
                 for (int q = 0; q < kNS; ++q)
 #pragma unroll
@@ -861,15 +945,20 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
                 uint64_t *row = off_ptr(ownN[q], R, NT) + pass0;
                 unsigned long long pc = 0;
 #pragma unroll
-                for (int kk = 0; kk < kCondPassWords; ++kk) {
-                    const uint32_t w = (uint32_t)(kk * kWave + lane);
-                    if (seedN[q] && w == (vN[q] >> 6) - pass0) acc[q][kk] |= 1ull << (vN[q] & 63);
-                    if (w < cw) {
-                        if (sgN[q])
-                            store_row_word(&row[w], acc[q][kk]);
-                        else if (acc[q][kk])
-                            atomicOr((unsigned long long *)&row[w], acc[q][kk]);
-                        if (aliasN[q]) pc += (unsigned long long)__popcll(acc[q][kk]);
+                for (int kk = 0; kk < kCondPassWords; kk += kCondVec) {
+                    const uint32_t w = cond_word(kk, lane);
+#pragma unroll
+                    for (int j = 0; j < kCondVec; ++j) {
+                        if (seedN[q] && w + j == (vN[q] >> 6) - pass0) acc[q][kk + j] |= 1ull << (vN[q] & 63);
+                        if (aliasN[q] && w + j < cw) pc += (unsigned long long)__popcll(acc[q][kk + j]);
+                    }
+                    if (sgN[q]) {
+                        store_words(row, w, cw, &acc[q][kk]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < kCondVec; ++j)
+                            if (w + j < cw && acc[q][kk + j])
+                                atomicOr((unsigned long long *)&row[w + j], acc[q][kk + j]);
                     }
                 }
                 if (aliasN[q]) {
@@ -963,8 +1052,25 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
         }
         // C. release successor components (once per node: first chunk)
         if (ch == 0) {
+            // from the node's links where it has them, else edge-parallel
+            // over its out-edges
+            bool walk_out = at;
+            if (g.xout_cnt && at) {
+                const uint32_t oc = g.xout_cnt[mine];
+                if (oc <= kCondLinks) {
+                    walk_out = false;
+                    for (uint32_t r = 0; r < oc; ++r) {
+                        const uint32_t si = g.xout[(uint64_t)mine * kCondLinks + r];
+                        const uint32_t cx = si / kStripes;
+                        if (atomicSub(&indeg[si], 1u) == 1u && atomicSub(&pending[cx], 1u) == 1u) {
+                            lev[cx] = L + 1;
+                            ++released;
+                        }
+                    }
+                }
+            }
             uint32_t ob = 0, oe = 0;
-            if (at) {
+            if (walk_out) {
                 ob = g.out_off[q];
                 oe = g.out_off[q + 1];
             }

@@ -207,7 +207,13 @@ struct ProdGraph {
     const InTrans *in_tr;          // per target state: (source state, label)
     const InTrans *out_tr;         // per source state: (target state in .src, label)
     const uint64_t *src_mask;      // sources searched ([ceil(n/64)] bits), null = all
+    // condensation links (written by k_cond_count, read by the level kernel;
+    // null = not kept): per node up to kCondLinks components it is entered
+    // from and stripe counters it retires, with counts (kCondLinks + 1 in
+    // xin_cnt: more, walk the edges instead)
+    uint32_t *xin_cnt, *xin, *xout_cnt, *xout;
 };
+constexpr uint32_t kCondLinks = 4;
 
 // condense.hip
 hipError_t launch_trim(const ProdGraph &g, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
@@ -274,14 +280,36 @@ hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_
 // parameter, at most 16; with one node per step 13 measured fastest, ahead
 // of 8, 9 and 16: equal chunks avoid a short last chunk that costs a whole
 // work item, and fewer chunks repeat the predecessor listing less often)
+// The row phase moves CFPQ_COND_VEC words per lane access (1: 8-byte, 2:
+// 16-byte loads and stores; with 2, chunks hold whole pairs of words, so a
+// chunk starts 16-byte aligned, rows being 64-byte aligned).  A compile-time
+// tuning parameter: 16-byte accesses (14 words per lane) measured slower,
+// 65.5 against 54.5 us per level launch on the RPQ workload at n = 10^5.
+#ifndef CFPQ_COND_VEC
+#define CFPQ_COND_VEC 1
+#endif
 #ifndef CFPQ_COND_LANE_WORDS
+#if CFPQ_COND_VEC == 2
+#define CFPQ_COND_LANE_WORDS 14
+#else
 #define CFPQ_COND_LANE_WORDS 13
 #endif
+#endif
+static_assert(CFPQ_COND_VEC == 1 || CFPQ_COND_VEC == 2, "8- or 16-byte row accesses");
+static_assert(CFPQ_COND_LANE_WORDS % CFPQ_COND_VEC == 0, "whole vectors per lane");
 constexpr uint32_t kCondChunkWords = CFPQ_COND_LANE_WORDS * 64;
-__host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) { return (Pn + kCondChunkWords - 1) / kCondChunkWords; }
+static_assert(kCondChunkWords % CFPQ_COND_VEC == 0, "chunk capacity in whole vectors");
+// equal widths, rounded up to whole vectors (never above the capacity); the
+// count follows from the width, so the last chunk is never empty
 __host__ __device__ inline uint32_t cond_chunk_words(uint32_t Pn) {
-    const uint32_t c = cond_chunks(Pn);
-    return c ? (Pn + c - 1) / c : kCondChunkWords;
+    if (Pn == 0) return kCondChunkWords;
+    const uint32_t c = (Pn + kCondChunkWords - 1) / kCondChunkWords;
+    const uint32_t w = (Pn + c - 1) / c;
+    return (w + CFPQ_COND_VEC - 1) / CFPQ_COND_VEC * CFPQ_COND_VEC;
+}
+__host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) {
+    const uint32_t w = cond_chunk_words(Pn);
+    return (Pn + w - 1) / w;
 }
 
 // Fused small-graph fixpoint: one workgroup runs a whole query.
