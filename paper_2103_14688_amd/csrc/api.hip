@@ -1009,13 +1009,24 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
         w.iter = it; w.ctr = d_ctr; w.slot_base = slot;
         w.chg = d_chg; w.prev_act = dact[cur]; w.rows_ctr = wb_rows;
+        // the summaries of the rows it changes come out of the write-back
+        // itself (every row whose dNT or NT row changes is visited);
+        // CFPQ_WB_SUMMARY = 0 rebuilds them in a pass of their own
+#ifndef CFPQ_WB_SUMMARY
+#define CFPQ_WB_SUMMARY 1
+#endif
+        w.sum_pitch = sum_pitch;
+        if (CFPQ_WB_SUMMARY) {
+            w.dsum = use_sum ? dsum.as<uint64_t>() : nullptr;
+            w.nsum = use_nsum ? nsum.as<uint64_t>() : nullptr;
+        }
         if ((st = prof_mark(0)) != CFPQ_OK) return st;
         HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
         if ((st = prof_mark(1)) != CFPQ_OK) return st;
         cur ^= 1;
-        if (use_sum)
+        if (use_sum && !w.dsum)
             HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dact[cur], dsum.as<uint64_t>(), sum_pitch, s));
-        if (use_nsum)
+        if (use_nsum && !w.nsum)
             HIP_TRY(launch_row_summary(d_NT, nB, n, P, Pn, dact[cur], nsum.as<uint64_t>(), sum_pitch, s));
         if ((st = fetch(slot, nB)) != CFPQ_OK) return st;
         if (prof) {

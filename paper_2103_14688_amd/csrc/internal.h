@@ -129,6 +129,11 @@ struct WritebackArgs {
     const uint64_t *chg;
     const uint64_t *prev_act;
     unsigned long long *rows_ctr;  // optional (profiling): rows visited, per box [nB]
+    // optional: summaries of the visited rows ([nB][n][sum_pitch], bit w % 64
+    // of word w / 64 set iff word w is non-zero) of dNT and NT, written here
+    // instead of by a separate pass over the rows
+    uint64_t *dsum, *nsum;
+    uint32_t sum_pitch;
 };                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip

@@ -968,6 +968,15 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
             }
         }
         if (dnt) dnt[k] = nw;
+        if (a.dsum || a.nsum) {
+            // lane l holds word 64 i + l: one summary word per step
+            const uint64_t dm = __ballot(nw != 0), nm = __ballot((old | nw) != 0);
+            const uint64_t so = ((uint64_t)N * a.n + v) * a.sum_pitch + (k - (uint32_t)lane) / kWave;
+            if (lane == 0) {
+                if (a.dsum) a.dsum[so] = dm;
+                if (a.nsum) a.nsum[so] = nm;
+            }
+        }
     }
     any_row = __ballot(any) != 0;
 }
@@ -1341,6 +1350,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr; wb.fresh = 0; wb.row_nz = nullptr;
     wb.state_flags = nullptr; wb.multi = nullptr; wb.skip_if[0] = wb.skip_if[1] = nullptr;
     wb.chg = nullptr; wb.prev_act = nullptr; wb.rows_ctr = nullptr;
+    wb.dsum = nullptr; wb.nsum = nullptr; wb.sum_pitch = 0;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     const bool narrow = Q.Pn <= kNarrowWords;
