@@ -451,6 +451,39 @@ def paths_workload(args):
             "paths_per_pair_max": int(max(counts)), "edges_returned": edges}
 
 
+def peredge_workload(args):
+    """The closure arms on small instances of the workloads: the literal
+    per-edge insertion (Sec. 3.1.1), the frontier-incremental levels and the
+    closure recomputed from scratch each iteration; ms per query and the
+    pairs each found (equal)."""
+    import synth
+    from paper_2103_14688_amd import cfpq, rsm
+
+    cases = [("brackets n=256", synth.erdos_renyi(256, seed=synth.BASE_SEED + 1), "cfg", synth.BRACKETS),
+             ("samegen G1 n=500", synth.hierarchy(500, seed=synth.BASE_SEED + 3)[0], "cfg", synth.SAME_GEN_G1),
+             ("samegen G1 n=1000", synth.hierarchy(1000, seed=synth.BASE_SEED + 3)[0], "cfg", synth.SAME_GEN_G1),
+             ("alias n=500 (clusters 16..64)", synth.clustered(500, cluster=(16, 64), seed=synth.BASE_SEED + 4),
+              "cfg", synth.MEM_ALIAS),
+             ("alias n=1000 (clusters 16..64)", synth.clustered(1000, cluster=(16, 64), seed=synth.BASE_SEED + 4),
+              "cfg", synth.MEM_ALIAS),
+             ("rpq n=5000", synth.powerlaw(5000), "regex", synth.RPQ_C2)]
+    out = {"workload": "closure arms: per-edge insertion vs frontier levels vs recomputed", "cases": []}
+    for name, g, kind, text in cases:
+        R = rsm.from_regex(text, g.labels) if kind == "regex" else rsm.from_grammar(text, g.labels)
+        graph, q = cfpq.Graph.from_synth(g), cfpq.Query(R)
+        row = {"case": name, "n": g.n, "states": R.n_states}
+        arms = [("peredge", {"strategy": cfpq.STRATEGY_PEREDGE}), ("levels", {"strategy": cfpq.STRATEGY_LEVELS})]
+        if kind != "regex":
+            arms.append(("recomputed", {"strategy": cfpq.STRATEGY_LEVELS, "recompute": True}))
+        for label, opts in arms:
+            _, dt, r = timed_queries(lambda: cfpq.query(graph, q, **opts), 2, 1)
+            row[label] = {"ms": dt * 1e3, "pairs": r.count(0), "iterations": r.stats()[0]}
+            r.close()
+        print(f"# {json.dumps(row)}", file=sys.stderr, flush=True)
+        out["cases"].append(row)
+    return out
+
+
 BLOCKS = ["brackets", "rpq_four_state", "samegen50k", "samegen200k", "alias", "serving"]
 
 
@@ -471,7 +504,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--blocks", default=",".join(BLOCKS),
                     help="workload blocks to add to the line (comma list of " + ",".join(BLOCKS) + ", or none)")
-    ap.add_argument("--only", choices=BLOCKS + ["paths"], default=None,
+    ap.add_argument("--only", choices=BLOCKS + ["paths", "peredge"], default=None,
                     help="run just this block and print it as the JSON line (no headline)")
     ap.add_argument("--grammar-n", type=int, default=0, help="--only samegen*/alias: graph size override")
     ap.add_argument("--serve-queries", type=int, default=2000)
@@ -520,6 +553,8 @@ def main():
             out = block_grammar(args, "alias", args.grammar_n or 20000, 5, 1, 8000)
         elif name == "serving":
             out = block_serving(args)
+        elif name == "peredge":
+            out = peredge_workload(args)
         else:
             out = paths_workload(args)
         out["block_wall_s"] = time.perf_counter() - t

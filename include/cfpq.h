@@ -146,8 +146,9 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *                workgroup; needs states * n <= 65536, else CFPQ_ERR_LIMIT;
  *                keep_rank and keep_blocks give CFPQ_ERR_INVALID; never
  *                picked by AUTO: it is the comparison arm of the method's
- *                complexity argument).  AUTO picks FUSED for small graphs,
- *                CONDENSED for other regular queries, LEVELS otherwise.
+ *                complexity argument).  AUTO picks FUSED for graphs of at
+ *                most 512 vertices (and at most 64 boxes), CONDENSED for
+ *                other regular queries, LEVELS otherwise.
  *                A CONDENSED query on a graph that has run one before goes
  *                out in one piece, sized by the launch chains the previous
  *                one needed, with a single host read at the end (steps the

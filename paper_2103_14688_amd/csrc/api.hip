@@ -635,7 +635,10 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     // sparse nonterminal product in the seed: ELL lists of the source rows and
     // an LDS row accumulator per wavefront (tiles up to kSparseMaxWords words)
     const bool sparse_nt = !p.nt_src.empty() && G <= kSparseMaxWords && o.nt_mode != CFPQ_NT_ROWS;
-    if (sparse_nt && !ell.alloc(al, (uint64_t)nQ * n * (kEll + 1) * 4, s))
+    // counts [nQ n] (padded to 4 entries), then the lists, 128-byte aligned
+    // (the product loads them 16 bytes at a time)
+    const uint64_t ell_pad = ((uint64_t)nQ * n + 31) / 32 * 32;
+    if (sparse_nt && !ell.alloc(al, (ell_pad + (uint64_t)nQ * n * kEll) * 4, s))
         return fail(CFPQ_ERR_OOM, "device allocation failed (sparse product index)");
     // source rows with more than kEll bits go through the LDS-blocked dense
     // product: their bitset [nQ][Pn] and its coarse array [nQ][Pbs]
@@ -734,7 +737,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     uint64_t *d_dns = dense_buf.as<uint64_t>(), *d_dblk = d_dns ? d_dns + (uint64_t)nQ * Pn : nullptr;
     DenseArgs dargs{};
     dargs.dns = d_dns; dargs.dblk = d_dblk; dargs.nt_dst = tb.nt_dst; dargs.n_nt_dst = (uint32_t)p.nt_dst.size();
-    dargs.ell_idx = sparse_nt ? ell.as<uint32_t>() + (uint64_t)nQ * n : nullptr;
+    dargs.ell_idx = sparse_nt ? ell.as<uint32_t>() + ell_pad : nullptr;
     // the dense product: ELL build marks dense rows, the sparse product leaves
     // them, the dense product ORs them in; a.bytes_ctr is the sparse one's
     auto dense_product = [&](GatherArgs &ga, uint64_t *extra, const uint64_t *extra_act) -> cfpq_status {
@@ -850,7 +853,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             if (sparse_nt) {
                 // the product rows go to the other frontier buffer and the third
                 // activity bitset, both unused until the first level
-                uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
+                uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + ell_pad;
                 HIP_TRY(launch_fill(d_dns, dense_words, 0, s));
                 HIP_TRY(launch_ell_build_dense(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt,
                                                ell_idx, nullptr, Pn, nullptr, d_dns, d_dblk, Pbs, s));
@@ -941,7 +944,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                     } else if (lsparse) {
                         HIP_TRY(launch_fill(xact.as<uint64_t>(), aw, 0, s));
                         HIP_TRY(launch_fill(d_dns, dense_words, 0, s));
-                        uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + (uint64_t)nQ * n;
+                        uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + ell_pad;
                         const unsigned long long *cp =
                             prev == kNoSlot ? nullptr : d_ctr + (uint64_t)prev * kSlotWords;
                         HIP_TRY(launch_ell_build_dense(a.src, G, 0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(),
@@ -1735,10 +1738,17 @@ cfpq_status check_opts(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     return CFPQ_OK;
 }
 
+// AUTO runs a single query fused up to 512 vertices: rows of at most 8 words
+// get a thread each there; past that a wavefront per row makes the one
+// workgroup 10x slower (n = 512 -> 640: brackets 1.8 -> 18 ms, same
+// generation 0.9 -> 10 ms, alias 3.7 -> 65 ms), while the multi-launch
+// strategies take 0.5-5 ms at these sizes
+constexpr uint32_t kFusedAutoMaxN = 512;
+
 bool use_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
     if (o.strategy == CFPQ_STRATEGY_FUSED) return true;
     if (o.strategy != CFPQ_STRATEGY_AUTO) return false;
-    return fused_ok(g, r) && g.n <= 1024;
+    return fused_ok(g, r) && g.n <= kFusedAutoMaxN;
 }
 
 cfpq_status run_big(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o, cfpq_result_s &res) {

@@ -250,6 +250,28 @@ __device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t 
     }
 }
 
+// two rows at once: every load of both is issued before any is used (two =
+// false: both pointers name the same row, counted once)
+#ifndef CFPQ_GATHER_PAIR
+#define CFPQ_GATHER_PAIR 0
+#endif
+__device__ __forceinline__ void or_row2(uint64_t (&acc)[kChunks], const uint64_t *r1, const uint64_t *r2,
+                                        uint32_t pass0, uint32_t gw, int lane, unsigned long long &by, bool two) {
+    uint64_t x1[kChunks], x2[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const uint32_t w = pass0 + c * kWave + lane;
+        x1[c] = w < gw ? r1[c * kWave + lane] : 0ull;
+        x2[c] = w < gw ? r2[c * kWave + lane] : 0ull;
+    }
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+        const uint32_t w = pass0 + c * kWave + lane;
+        acc[c] |= x1[c] | x2[c];
+        if (w < gw) by += two ? 16 : 8;
+    }
+}
+
 // One wavefront computes the new source bits of product row (f, v) over the
 // source tile of a.  SEED: the OR runs over the new graph edges only (the
 // Kronecker product with A2: every graph edge in the first iteration, the
@@ -290,12 +312,26 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     }
                     uint64_t m = __ballot(ok);
                     fed |= (m != 0);
+#if CFPQ_GATHER_PAIR
+                    // two rows per step, all their loads in flight together
+                    while (m) {
+                        const int j1 = __ffsll((unsigned long long)m) - 1;
+                        m &= m - 1;
+                        const int j2 = m ? __ffsll((unsigned long long)m) - 1 : j1;
+                        if (m) m &= m - 1;
+                        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)x, j1);
+                        const uint32_t x2 = (uint32_t)__builtin_amdgcn_readlane((int)x, j2);
+                        or_row2(acc, rows + (uint64_t)x1 * a.src_pitch, rows + (uint64_t)x2 * a.src_pitch, pass0,
+                                a.gw, lane, by, j2 != j1);
+                    }
+#else
                     while (m) {
                         const int j = __ffsll((unsigned long long)m) - 1;
                         m &= m - 1;
                         const uint32_t xj = (uint32_t)__builtin_amdgcn_readlane((int)x, j);
                         or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane, by);
                     }
+#endif
                 }
             } else {
                 if (a.extra) continue;  // done by the sparse or matrix-core product, OR-ed in below
@@ -313,10 +349,11 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     if (!live) continue;
                     uint64_t wb = 0;
                     if (k < a.Pn && ((live >> lane) & 1ull)) {
-                        // the activity word first: the selector is read only
-                        // where some source row is live
-                        const uint64_t sa = sact[k];
-                        if (sa) wb = sel[k] & sa;
+                        // activity and selector words loaded together (one
+                        // round trip; the summaries already say both may be
+                        // non-zero)
+                        const uint64_t sa = sact[k], sv = sel[k];
+                        wb = sv & sa;
                     }
                     uint64_t m = __ballot(wb != 0);
                     fed |= (m != 0);
@@ -418,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
                     atomicOr((unsigned long long *)&dns[(uint64_t)s * Pn + (x >> 6)], 1ull << (x & 63));
                     mark_blk(dblk, Pbs, s, x);
                     // a dense row's list holds its block mask instead (two
-                    // 32-bit entries: the list is only 4-byte aligned)
+                    // 32-bit entries)
                     ell_idx[cell * kEll] = (uint32_t)bmask;
                     ell_idx[cell * kEll + 1] = (uint32_t)(bmask >> 32);
                 }
@@ -498,11 +535,11 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                 if (!live) continue;
                 uint64_t wb = 0;
                 if (k < a.Pn && ((live >> lane) & 1ull)) {
-                    // the activity word first: the selector is read only
-                    // where some source row is live
-                    const uint64_t sa = sact[k];
-                    if (sa) wb = sel[k] & sa;
-                    by += sa ? 16 : 8;
+                    // activity and selector words loaded together (one round
+                    // trip; the summaries already say both may be non-zero)
+                    const uint64_t sa = sact[k], sv = sel[k];
+                    wb = sv & sa;
+                    by += 16;
                 }
                 uint64_t m = __ballot(wb != 0);
                 if (m && !cleared) {
@@ -521,16 +558,34 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
                     const uint32_t xb = (k0 + (uint32_t)j) * 64u;
                     const bool mine = (bits >> lane) & 1ull;
                     const uint64_t cell = (uint64_t)tr.src * a.n + xb + (uint32_t)lane;
-                    const uint32_t cnt = mine ? ell_cnt[cell] : 0u;
+                    // the count and the list's first four entries are loaded
+                    // together (one memory round trip for short lists); the
+                    // lists are 128-byte aligned, 16 bytes per load
+                    const uint4 *idx4 = reinterpret_cast<const uint4 *>(ell_idx + cell * kEll);
+                    uint32_t cnt = 0;
+                    uint4 e0 = make_uint4(0, 0, 0, 0);
+                    if (mine) {
+                        cnt = ell_cnt[cell];
+                        e0 = idx4[0];
+                    }
                     // rows beyond an ELL list: ORed whole here, unless they are
                     // left to the blocked dense product
                     const bool dense = cnt == kEllDense || (cnt == kEllBlocked && !a.dense_apart);
                     const bool apart = cnt == kEllBlocked && a.dense_apart;
-                    if (!dense && !apart) {
-                        const uint32_t *idx = ell_idx + cell * kEll;
-                        for (uint32_t e = 0; e < cnt; ++e) {
-                            const uint32_t u = idx[e];
-                            atomicOr(&acc[u >> 6], 1ull << (u & 63));
+                    if (!dense && !apart && cnt) {
+                        auto put = [&](uint32_t u) { atomicOr(&acc[u >> 6], 1ull << (u & 63)); };
+                        put(e0.x);
+                        if (cnt > 1) put(e0.y);
+                        if (cnt > 2) put(e0.z);
+                        if (cnt > 3) put(e0.w);
+                        // the rest eight entries per step, both loads in flight
+                        for (uint32_t e = 4; e < cnt; e += 8) {
+                            const uint4 p = idx4[e / 4];
+                            const uint4 q = e + 4 < cnt ? idx4[e / 4 + 1] : make_uint4(0, 0, 0, 0);
+                            const uint32_t v8[8] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w};
+#pragma unroll
+                            for (uint32_t i = 0; i < 8; ++i)
+                                if (e + i < cnt) put(v8[i]);
                         }
                     }
                     if (mine) by += 4ull * (1 + (dense || apart ? 0u : cnt));
