@@ -374,6 +374,7 @@ struct Plan {
     std::vector<uint32_t> is_start;      // per state: initial state of its box
     std::vector<uint32_t> nt_src;        // source states of box-labelled transitions
     std::vector<uint32_t> nt_dst;        // target states of box-labelled transitions
+    std::vector<uint32_t> f_box;         // per state: the box of its only box-labelled in-transition, else kNoBox
 };
 
 Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
@@ -431,6 +432,17 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
         }
     for (size_t i = 0; i < r.t_sym.size(); ++i)
         if (r.t_sym[i] >= r.n_terms) p.box_used[r.t_sym[i] - r.n_terms] = 1;
+    p.f_box.assign(p.nQ, kNoBox);
+    {
+        std::vector<uint32_t> calls(p.nQ, 0);
+        for (size_t i = 0; i < r.t_sym.size(); ++i)
+            if (r.t_sym[i] >= r.n_terms) {
+                calls[r.t_dst[i]]++;
+                p.f_box[r.t_dst[i]] = r.t_sym[i] - r.n_terms;
+            }
+        for (uint32_t q = 0; q < p.nQ; ++q)
+            if (calls[q] != 1) p.f_box[q] = kNoBox;
+    }
     return p;
 }
 
@@ -438,7 +450,8 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
 struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
-             *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr, *nt_dst = nullptr;
+             *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr, *nt_dst = nullptr,
+             *f_box = nullptr;
     InTrans *in_tr = nullptr, *out_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
@@ -447,7 +460,8 @@ struct Tables {
 // offset of each part in it
 struct TableImage {
     std::vector<uint8_t> host;
-    size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src, nt_dst;
+    size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src, nt_dst,
+        f_box;
 };
 
 void pack_tables(const Plan &p, TableImage &im) {
@@ -472,6 +486,7 @@ void pack_tables(const Plan &p, TableImage &im) {
     im.is_start = put(p.is_start.data(), p.is_start.size() * 4);
     im.nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
     im.nt_dst = put(p.nt_dst.data(), p.nt_dst.size() * 4);
+    im.f_box = put(p.f_box.data(), p.f_box.size() * 4);
 }
 
 // table pointers into a device copy of the image at b
@@ -489,6 +504,7 @@ void bind_tables(const TableImage &im, uint8_t *b, Tables &t) {
     t.is_start = (uint32_t *)(b + im.is_start);
     t.nt_src = (uint32_t *)(b + im.nt_src);
     t.nt_dst = (uint32_t *)(b + im.nt_dst);
+    t.f_box = (uint32_t *)(b + im.f_box);
 }
 
 cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
@@ -784,6 +800,38 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         if (!ones.alloc(al, (uint64_t)nB * Pn * 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed");
         HIP_TRY(launch_fill(ones.as<uint64_t>(), (uint64_t)nB * Pn, ~0ull, s));
     }
+    // seed deduplication (incremental closure with the sparse product): after
+    // each write-back, classes of equal new-edge rows; in the next seed only
+    // one row per class computes the product of a target state with a single
+    // box-labelled in-transition, the others read its row
+#ifndef CFPQ_SEED_DEDUP
+#define CFPQ_SEED_DEDUP 1
+#endif
+    bool dedup = CFPQ_SEED_DEDUP && sparse_nt && use_sum && !scratch && (uint64_t)nB * n < (1ull << 31);
+    if (dedup) {
+        bool any_box = false;
+        for (uint32_t f : p.f_box) any_box |= f != kNoBox;
+        dedup = any_box;
+    }
+    DevBuf dd_buf;
+    uint64_t dd_mask = 0;
+    uint64_t *dd_hash = nullptr;
+    uint32_t *dd_rep = nullptr, *dd_vals = nullptr;
+    unsigned long long *dd_keys = nullptr;
+    bool rep_valid = false;   // dd_rep holds the classes of the current dNT rows
+    if (dedup) {
+        const uint64_t rows = (uint64_t)nB * n;
+        uint64_t slots = 2;
+        while (slots < 2 * rows) slots <<= 1;
+        dd_mask = slots - 1;
+        // hashes [rows] u64, table keys [slots] u64, values [slots] u32, reps [rows] u32
+        const uint64_t words = rows + slots + slots / 2 + (rows + 1) / 2;
+        if (!dd_buf.alloc(al, words * 8, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (seed classes)");
+        dd_hash = dd_buf.as<uint64_t>();
+        dd_keys = (unsigned long long *)(dd_hash + rows);
+        dd_vals = (uint32_t *)(dd_hash + rows + slots);
+        dd_rep = (uint32_t *)(dd_hash + rows + slots + slots / 2);
+    }
 
     PinnedCounters pc;
     if (!pc.ensure(4096 * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
@@ -849,6 +897,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             a.slot_prev = kNoSlot; a.slot_cur = slot; a.seed_terms = (it == 1) || scratch;
             a.extra = nullptr; a.extra_act = nullptr; a.bytes_ctr = sp_bytes;
             a.dense_apart = sparse_nt ? 1u : 0u;
+            a.rep = rep_valid ? dd_rep : nullptr; a.f_box = tb.f_box;
             if ((st = prof_mark3(0, 0)) != CFPQ_OK) return st;
             if (sparse_nt) {
                 // the product rows go to the other frontier buffer and the third
@@ -884,6 +933,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 }
             }
             uint32_t prev = slot++;
+            a.rep = nullptr;   // the levels' products use M2, not the new edges
             uint64_t rows_in = prof ? pc.h[2] : 0;   // frontier rows feeding the next level
             // incremental closure: frontier levels until one adds nothing
             uint32_t li = 1;
@@ -1023,6 +1073,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             w.dsum = use_sum ? dsum.as<uint64_t>() : nullptr;
             w.nsum = use_nsum ? nsum.as<uint64_t>() : nullptr;
         }
+        w.dhash = dedup ? dd_hash : nullptr;
         if ((st = prof_mark(0)) != CFPQ_OK) return st;
         HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
         if ((st = prof_mark(1)) != CFPQ_OK) return st;
@@ -1031,6 +1082,11 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dact[cur], dsum.as<uint64_t>(), sum_pitch, s));
         if (use_nsum && !w.nsum)
             HIP_TRY(launch_row_summary(d_NT, nB, n, P, Pn, dact[cur], nsum.as<uint64_t>(), sum_pitch, s));
+        if (dedup) {
+            HIP_TRY(launch_dedup(nB, n, P, Pn, dact[cur], dd_hash, d_dNT, dsum.as<uint64_t>(), sum_pitch, dd_keys,
+                                 dd_vals, dd_mask, dd_rep, s));
+            rep_valid = true;
+        }
         if ((st = fetch(slot, nB)) != CFPQ_OK) return st;
         if (prof) {
             auto &pw = res.prof[CFPQ_KERNEL_WRITEBACK];

@@ -81,7 +81,15 @@ struct GatherArgs {
     // left to k_nt_dense; every target row with a selected source row is
     // still written and flagged (the dense product ORs into it afterwards)
     uint32_t dense_apart;
+    // optional (seed): representative rows of the selector classes.  For a
+    // target state f with exactly one box-labelled incoming transition (box
+    // f_box[f], else kNoBox) and an active selector row (N, v), rep[N n + v]
+    // is a row with the same selector contents; the product is computed for
+    // representatives only, and (f, v) reads the row of (f, rep).  null = off
+    const uint32_t *rep;
+    const uint32_t *f_box;
 };
+constexpr uint32_t kNoBox = 0xFFFFFFFFu;
 // summary of the rows [nB][n][P] whose bit is set in act ([nB][Pn] bits;
 // other rows' summaries are left as they are): bit w % 64 of summary word
 // w / 64 set iff word w is non-zero
@@ -134,6 +142,9 @@ struct WritebackArgs {
     // instead of by a separate pass over the rows
     uint64_t *dsum, *nsum;
     uint32_t sum_pitch;
+    // optional: per row [nB][n] a 64-bit hash of its new edges (dNT row),
+    // written for rows that gained edges (non-zero)
+    uint64_t *dhash;
 };                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip
@@ -195,6 +206,14 @@ struct MfmaArgs {
 };
 hipError_t launch_nt_mfma(const MfmaArgs &a, hipStream_t s);
 hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s);
+// Seed deduplication: classes of equal dNT rows among the active ones (act
+// [nB][Pn]), from the write-back's row hashes; keys/vals is an open-addressing
+// table of mask + 1 >= 2 nB n slots (cleared here).  rep[N n + v] := a row of
+// box N with the same contents (the least row index of its hash bucket when
+// the rows compare equal word for word, else v itself).
+hipError_t launch_dedup(uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *act, const uint64_t *dhash,
+                        const uint64_t *dNT, const uint64_t *dsum, uint32_t sum_pitch, unsigned long long *keys,
+                        uint32_t *vals, uint64_t mask, uint32_t *rep, hipStream_t s);
 hipError_t launch_popcount(const uint64_t *p, uint64_t rows, uint32_t pitch, uint32_t words,
                            unsigned long long *out, hipStream_t s);
 hipError_t launch_hash(const uint64_t *NTb, uint32_t n, uint32_t P, unsigned long long *out,

@@ -250,28 +250,6 @@ __device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t 
     }
 }
 
-// two rows at once: every load of both is issued before any is used (two =
-// false: both pointers name the same row, counted once)
-#ifndef CFPQ_GATHER_PAIR
-#define CFPQ_GATHER_PAIR 0
-#endif
-__device__ __forceinline__ void or_row2(uint64_t (&acc)[kChunks], const uint64_t *r1, const uint64_t *r2,
-                                        uint32_t pass0, uint32_t gw, int lane, unsigned long long &by, bool two) {
-    uint64_t x1[kChunks], x2[kChunks];
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-        const uint32_t w = pass0 + c * kWave + lane;
-        x1[c] = w < gw ? r1[c * kWave + lane] : 0ull;
-        x2[c] = w < gw ? r2[c * kWave + lane] : 0ull;
-    }
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-        const uint32_t w = pass0 + c * kWave + lane;
-        acc[c] |= x1[c] | x2[c];
-        if (w < gw) by += two ? 16 : 8;
-    }
-}
-
 // One wavefront computes the new source bits of product row (f, v) over the
 // source tile of a.  SEED: the OR runs over the new graph edges only (the
 // Kronecker product with A2: every graph edge in the first iteration, the
@@ -312,26 +290,12 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                     }
                     uint64_t m = __ballot(ok);
                     fed |= (m != 0);
-#if CFPQ_GATHER_PAIR
-                    // two rows per step, all their loads in flight together
-                    while (m) {
-                        const int j1 = __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
-                        const int j2 = m ? __ffsll((unsigned long long)m) - 1 : j1;
-                        if (m) m &= m - 1;
-                        const uint32_t x1 = (uint32_t)__builtin_amdgcn_readlane((int)x, j1);
-                        const uint32_t x2 = (uint32_t)__builtin_amdgcn_readlane((int)x, j2);
-                        or_row2(acc, rows + (uint64_t)x1 * a.src_pitch, rows + (uint64_t)x2 * a.src_pitch, pass0,
-                                a.gw, lane, by, j2 != j1);
-                    }
-#else
                     while (m) {
                         const int j = __ffsll((unsigned long long)m) - 1;
                         m &= m - 1;
                         const uint32_t xj = (uint32_t)__builtin_amdgcn_readlane((int)x, j);
                         or_row(acc, rows + (uint64_t)xj * a.src_pitch, pass0, a.gw, lane, by);
                     }
-#endif
                 }
             } else {
                 if (a.extra) continue;  // done by the sparse or matrix-core product, OR-ed in below
@@ -371,9 +335,15 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                 }
             }
         }
-        if (a.extra && test_bit(a.extra_act + (uint64_t)f * a.Pn, v)) {
+        // the product row of (f, v), or of its class representative
+        uint32_t vx = v;
+        if (SEED && a.rep) {
+            const uint32_t Nf = a.f_box[f];
+            if (Nf != kNoBox && test_bit(a.sel_act + (uint64_t)Nf * a.Pn, v)) vx = a.rep[(uint64_t)Nf * a.n + v];
+        }
+        if (a.extra && test_bit(a.extra_act + (uint64_t)f * a.Pn, vx)) {
             fed = true;
-            or_row(acc, a.extra + ((uint64_t)f * a.n + v) * a.G + pass0, pass0, a.gw, lane, by);
+            or_row(acc, a.extra + ((uint64_t)f * a.n + vx) * a.G + pass0, pass0, a.gw, lane, by);
         }
         if (!fed) return false;  // no source row feeds (f, v): same in every pass
         uint64_t *trow = a.T + ((uint64_t)f * a.n + v) * a.P + a.w0 + pass0;
@@ -522,6 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32
             const uint32_t N = tr.sym - a.n_terms;
             if (!state_live(a, tr.src)) continue;   // no active row in the source state
             if (a.sel_act && !test_bit(a.sel_act + (uint64_t)N * a.Pn, v)) continue;
+            // another row of the same selector class computes this product
+            if (a.rep && a.f_box[f] == N && a.rep[(uint64_t)N * a.n + v] != v) continue;
             const uint64_t *sel = a.sel + ((uint64_t)N * a.n + v) * a.P;
             const uint64_t *sact = a.src_act + (uint64_t)tr.src * a.Pn;
             const uint64_t *ssum = a.sel_sum ? a.sel_sum + ((uint64_t)N * a.n + v) * a.sum_pitch : nullptr;
@@ -996,6 +968,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
     uint64_t *dnt = a.dNT ? a.dNT + ((uint64_t)N * a.n + v) * a.P : nullptr;
     bool any = false;
+    unsigned long long hs = 0;   // hash of the new edges: sum over non-zero words of a mix of (word, index)
     const uint32_t nch = cond_chunks(a.Pn), cwds = cond_chunk_words(a.Pn);
     for (uint32_t k = lane; k < a.Pn; k += kWave) {
         uint64_t acc = 0;
@@ -1013,6 +986,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
             if (!a.fresh) nt[k] = old | nw;
             any = true;
             cnt_box += (unsigned long long)__popcll(nw);
+            hs += splitmix64(nw ^ ((uint64_t)k * 0x9e3779b97f4a7c15ull));
             if (a.rank) {
                 uint64_t bits = nw;
                 while (bits) {
@@ -1034,6 +1008,10 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
         }
     }
     any_row = __ballot(any) != 0;
+    if (a.dhash && any_row) {
+        hs = wave_sum(hs);
+        if (lane == 0) a.dhash[(uint64_t)N * a.n + v] = hs ? hs : 1ull;
+    }
 }
 
 constexpr uint32_t kWbLdsBoxes = 64;   // boxes whose new-edge counts gather in LDS first
@@ -1123,6 +1101,88 @@ __global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
 
 hipError_t launch_writeback(const WritebackArgs &a, uint32_t grid, hipStream_t s) {
     hipLaunchKernelGGL(k_writeback, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// seed deduplication: equal dNT rows select the same rows, so their seed
+// products are equal; one representative per class computes it
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long dedup_key(uint64_t h, uint32_t N) {
+    const uint64_t k = splitmix64(h + N);
+    return k ? k : 1ull;   // 0 marks an empty slot
+}
+
+// a thread per row: insert the active rows' keys, each bucket keeping its
+// least row index (row ids N n + v)
+__global__ void k_dedup_insert(uint32_t nB, uint32_t n, uint32_t Pn, const uint64_t *act, const uint64_t *dhash,
+                               unsigned long long *keys, uint32_t *vals, uint64_t mask) {
+    const uint64_t rows = (uint64_t)nB * n;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t N = (uint32_t)(r / n), v = (uint32_t)(r % n);
+        if (!test_bit(act + (uint64_t)N * Pn, v)) continue;
+        const unsigned long long key = dedup_key(dhash[r], N);
+        // linear probing; the table has at least twice as many slots as rows,
+        // so an empty or matching slot is always found
+        for (uint64_t slot = key & mask;; slot = (slot + 1) & mask) {
+            const unsigned long long prev = atomicCAS(&keys[slot], 0ull, key);
+            if (prev == 0ull || prev == key) {
+                atomicMin(&vals[slot], (uint32_t)r);
+                break;
+            }
+        }
+    }
+}
+
+// a wavefront per active row: its bucket's least row, kept as representative
+// only if the two rows are equal (summaries, then the words they flag)
+__global__ __launch_bounds__(kBlock) void k_dedup_rep(uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn,
+                                                      const uint64_t *act, const uint64_t *dhash, const uint64_t *dNT,
+                                                      const uint64_t *dsum, uint32_t sum_pitch,
+                                                      const unsigned long long *keys, const uint32_t *vals,
+                                                      uint64_t mask, uint32_t *rep) {
+    const int lane = __lane_id();
+    const uint64_t rows = (uint64_t)nB * n;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t r = wave; r < rows; r += nwaves) {
+        const uint32_t N = (uint32_t)(r / n), v = (uint32_t)(r % n);
+        if (!test_bit(act + (uint64_t)N * Pn, v)) continue;
+        const unsigned long long key = dedup_key(dhash[r], N);
+        uint64_t slot = key & mask;
+        while (keys[slot] != key) slot = (slot + 1) & mask;   // inserted above: found
+        const uint32_t c = vals[slot];
+        uint32_t out = v;
+        if (c != (uint32_t)r && c / n == N) {
+            const uint64_t rc = c;
+            bool diff = false;
+            for (uint32_t k = lane; k < sum_pitch; k += kWave)
+                diff |= dsum[r * sum_pitch + k] != dsum[rc * sum_pitch + k];
+            if (!__ballot(diff)) {
+                for (uint32_t k = lane; k < Pn; k += kWave) {
+                    const uint64_t sw = dsum[r * sum_pitch + k / kWave];
+                    if ((sw >> (k & 63)) & 1ull) diff |= dNT[r * P + k] != dNT[rc * P + k];
+                }
+            }
+            if (!__ballot(diff)) out = c % n;
+        }
+        if (lane == 0) rep[r] = out;
+    }
+}
+
+hipError_t launch_dedup(uint32_t nB, uint32_t n, uint32_t P, uint32_t Pn, const uint64_t *act, const uint64_t *dhash,
+                        const uint64_t *dNT, const uint64_t *dsum, uint32_t sum_pitch, unsigned long long *keys,
+                        uint32_t *vals, uint64_t mask, uint32_t *rep, hipStream_t s) {
+    const uint64_t rows = (uint64_t)nB * n;
+    hipError_t e = launch_fill((uint64_t *)keys, mask + 1, 0, s);
+    if (e == hipSuccess) e = launch_fill((uint64_t *)vals, (mask + 1) / 2, ~0ull, s);   // u32 slots, pairs per word
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dedup_insert, dim3(grid_for(rows)), dim3(kBlock), 0, s, nB, n, Pn, act, dhash, keys, vals,
+                       mask);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dedup_rep, dim3(grid_for(rows * kWave)), dim3(kBlock), 0, s, nB, n, P, Pn, act, dhash, dNT,
+                       dsum, sum_pitch, keys, vals, mask, rep);
     return hipGetLastError();
 }
 
@@ -1398,6 +1458,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     a.sel_sum = nullptr; a.sum_pitch = 0;
     a.src_blk = nullptr; a.actn_blk = nullptr; a.Pbs = 0; a.chg = nullptr; a.bytes_ctr = nullptr;
     a.dense_apart = 0;
+    a.rep = nullptr;
+    a.f_box = nullptr;
 
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
@@ -1405,7 +1467,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     wb.ctr = nullptr; wb.slot_base = 0; wb.row_map = nullptr; wb.fresh = 0; wb.row_nz = nullptr;
     wb.state_flags = nullptr; wb.multi = nullptr; wb.skip_if[0] = wb.skip_if[1] = nullptr;
     wb.chg = nullptr; wb.prev_act = nullptr; wb.rows_ctr = nullptr;
-    wb.dsum = nullptr; wb.nsum = nullptr; wb.sum_pitch = 0;
+    wb.dsum = nullptr; wb.nsum = nullptr; wb.sum_pitch = 0; wb.dhash = nullptr;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     const bool narrow = Q.Pn <= kNarrowWords;
