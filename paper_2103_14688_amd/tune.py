@@ -8,7 +8,8 @@ A query's class is a key of measured features that decide which variant
 wins: the size class of the graph (log2 n), its mean degree class, the
 number of RSM states and boxes, whether the query has box-labelled
 transitions (a grammar) or not (a regular query, one productive iteration),
-and whether some box is nullable.  The first query of a class runs every
+and whether some box is nullable.  The candidates include the literal
+per-edge closure for small classes.  The first query of a class runs every
 candidate once (each a complete, correct query: the answer does not depend
 on the choice) and records the fastest; later queries of the class run the
 recorded choice.  Within a query the library switches formats by itself:
@@ -29,6 +30,7 @@ import time
 from . import cfpq
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "cfpq_gfx950", "tune.json")
+PEREDGE_MAX_NODES = 4096   # product nodes (upper bound from the class key) for the per-edge arm
 
 
 def features(graph, rsm):
@@ -59,6 +61,11 @@ def candidates(feat):
     out = []
     if small:
         out.append({"strategy": cfpq.STRATEGY_FUSED})
+    # the literal per-edge closure (Sec. 3.1.1) as an arm of its own where it
+    # finishes in well under a second (states * n up to 4096; its limit is
+    # 65536); it has never been the fastest, but the tuner measures, not assumes
+    if feat["states"] * (2 << feat["n_log2"]) <= PEREDGE_MAX_NODES:
+        out.append({"strategy": cfpq.STRATEGY_PEREDGE})
     if not feat["grammar"]:
         out.append({"strategy": cfpq.STRATEGY_CONDENSED})
         out.append({"strategy": cfpq.STRATEGY_LEVELS})

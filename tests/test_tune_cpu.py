@@ -43,6 +43,10 @@ def test_candidates_cover_strategies_modes_tiles_and_arms():
     assert any(o.get("tile_words", 0) > 1200 for o in c)
     small = tune.candidates(tune.features(FakeGraph(500, 1000), G))
     assert small[0]["strategy"] == cfpq.STRATEGY_FUSED
+    # the literal per-edge arm only where the product graph is small
+    B = rsm.from_grammar(synth.BRACKETS, ["a", "b"])
+    assert any(o["strategy"] == cfpq.STRATEGY_PEREDGE for o in tune.candidates(tune.features(FakeGraph(300, 600), B)))
+    assert not any(o["strategy"] == cfpq.STRATEGY_PEREDGE for o in c)   # same generation at n = 2e5
 
 
 def test_picks_fastest_and_persists(tmp_path, monkeypatch):
