@@ -582,6 +582,55 @@ struct PinnedCounters {
     }
 };
 
+// HIP events in a process-wide pool per device, like the pinned buffers:
+// creating and destroying a query's events costs more than recording them
+class EventPool {
+    std::mutex m_;
+    std::vector<std::pair<int, hipEvent_t>> free_;
+
+  public:
+    static EventPool &get() {
+        static EventPool *pool = new EventPool;
+        return *pool;
+    }
+    hipError_t take(int dev, hipEvent_t &e) {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            for (size_t i = 0; i < free_.size(); ++i)
+                if (free_[i].first == dev) {
+                    e = free_[i].second;
+                    free_[i] = free_.back();
+                    free_.pop_back();
+                    return hipSuccess;
+                }
+        }
+        return hipEventCreate(&e);
+    }
+    void put(int dev, hipEvent_t e) {
+        std::lock_guard<std::mutex> lk(m_);
+        free_.emplace_back(dev, e);
+    }
+};
+
+// a query's events, back to the pool when the query ends
+struct PooledEvents {
+    int dev = 0;
+    std::vector<hipEvent_t> v;
+    ~PooledEvents() {
+        for (hipEvent_t e : v) EventPool::get().put(dev, e);
+    }
+    hipError_t ensure(size_t k) {
+        if (v.empty()) (void)hipGetDevice(&dev);
+        while (v.size() < k) {
+            hipEvent_t e = nullptr;
+            hipError_t er = EventPool::get().take(dev, e);
+            if (er != hipSuccess) return er;
+            v.push_back(e);
+        }
+        return hipSuccess;
+    }
+};
+
 uint64_t *d_u64(const DevBuf &b) { return b.as<uint64_t>(); }
 
 bool max_iters_hit(const cfpq_query_opts &o, uint32_t it) { return o.max_iters && it > o.max_iters; }
@@ -1147,9 +1196,6 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
                             (b << kFlagBoxShift);
         }
     }
-    Tables tb;
-    cfpq_status st = upload_tables(p, al, s, tb);
-    if (st != CFPQ_OK) return st;
     const uint32_t n = p.n, P = p.P, Pn = p.Pn, nQ = p.nQ, nB = p.nB;
     const uint32_t N = nQ * n;
     const uint64_t qw = (uint64_t)nQ * n * P, bw = (uint64_t)nB * n * P;
@@ -1178,11 +1224,32 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     const uint64_t o_alive = o_fnz + al256(N64 + nzb + 64);
     const uint64_t o_act = o_alive + al256(N64);
     const uint64_t o_dnt = o_act + al256((uint64_t)nB * Pn * 8);
+    // the small tables and the closure rows T share the work allocation
+    // (one call into the caller's allocator); T is separate when the query
+    // keeps it (keep_blocks)
+    TableImage im;
+    pack_tables(p, im);
+    const uint64_t o_tbl = o_dnt + al256(nullable ? bw * 8 : 8);
+    const uint64_t o_T = o_tbl + al256(im.host.size());
     DevBuf T, work;
-    if (!T.alloc(al, qw * 8, s) || !res.NT.alloc(al, bw * 8, s) ||
-        !work.alloc(al, o_dnt + (nullable ? bw * 8 : 8), s))
+    if (!res.NT.alloc(al, bw * 8, s) || !work.alloc(al, o_T + (o.keep_blocks ? 0 : qw * 8), s) ||
+        (o.keep_blocks && !T.alloc(al, qw * 8, s)))
         return fail(CFPQ_ERR_OOM, "device allocation failed (condensed query)");
     uint8_t *wk = work.as<uint8_t>();
+    uint64_t *Tp = o.keep_blocks ? T.as<uint64_t>() : (uint64_t *)(wk + o_T);
+    // counter read-backs: [0, kCtr) launch counters, [kCtr, 2 kCtr) level
+    // counts, then the search frontier sizes; the table image goes behind
+    // them (pinned, so the upload needs no wait: the query's last read-back
+    // comes after it on the stream)
+    constexpr size_t kPinWords = 2 * (size_t)8192 + 8;
+    PinnedCounters pc;
+    const size_t img_words = (im.host.size() + 7) / 8;
+    if (!pc.ensure(kPinWords + img_words)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+    std::memcpy(pc.h + kPinWords, im.host.data(), im.host.size());
+    HIP_TRY(hipMemcpyAsync(wk + o_tbl, pc.h + kPinWords, im.host.size(), hipMemcpyHostToDevice, s));
+    Tables tb;
+    bind_tables(im, wk + o_tbl, tb);
+    cfpq_status st = CFPQ_OK;
     uint64_t *dnt_act = (uint64_t *)(wk + o_act), *dNT = (uint64_t *)(wk + o_dnt);
     if (o.keep_rank) {
         if (!res.rank.alloc(al, (uint64_t)nB * n * n, s)) return fail(CFPQ_ERR_OOM, "device allocation failed (rank)");
@@ -1206,22 +1273,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         pg.xout = pg.xin + (uint64_t)kCondLinks * Nu;
     }
 
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    struct EvGuard {
-        hipEvent_t *e;
-        ~EvGuard() {
-            for (int i = 0; i < 4; ++i)
-                if (e[i]) (void)hipEventDestroy(e[i]);
-        }
-    } evg{ev};
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    PooledEvents evp;
+    HIP_TRY(evp.ensure(4));
+    hipEvent_t *ev = evp.v.data();
     const bool prof = o.profile != 0;
     res.profiled = prof;
-
-    PinnedCounters pc;
-    // read-backs: [0, kCtr) launch counters, [kCtr, 2 kCtr) level counts,
-    // then the search frontier sizes
-    if (!pc.ensure(2 * kCtr + 8)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+    static_assert(2 * kCtr + 8 == kPinWords, "read-back area in front of the table image");
     uint32_t slot = 0;
     // a fresh zeroed counter per launch; the whole array is cleared when used up
     auto next_slot = [&](uint32_t k) -> cfpq_status {
@@ -1335,32 +1392,22 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     // clears lc[(L + 2) % kCtr] before level L + 1 writes it
     auto condense_setup = [&](const unsigned long long *skip_if) -> cfpq_status {
         HIP_TRY(launch_cond_count(pg, scc, size, stripe, skip_if, s));
-        HIP_TRY(launch_cond_seed(n, P, Pn, nQ, tb.starts, nB, scc, size, d_u64(T), nzf, res.src_mask.as<uint64_t>(),
+        HIP_TRY(launch_cond_seed(n, P, Pn, nQ, tb.starts, nB, scc, size, Tp, nzf, res.src_mask.as<uint64_t>(),
                                  skip_if, s));
         HIP_TRY(launch_cond_roots(N, scc, stripe, pending, lev, lc + 0, skip_if, s));
         HIP_TRY(launch_fill((uint64_t *)box_pairs, (uint64_t)nB * kWave, 0, s));
         HIP_TRY(launch_fill((uint64_t *)box_pairs + kBytesSlot, 2 * kWave, 0, s));
         return CFPQ_OK;
     };
-    std::vector<hipEvent_t> lev_ev;   // profiling: an event before each level launch, one after the chunk
-    struct PoolGuard {
-        std::vector<hipEvent_t> *v;
-        ~PoolGuard() {
-            for (hipEvent_t e : *v) (void)hipEventDestroy(e);
-        }
-    } pg_guard{&lev_ev};
+    PooledEvents lev_pool;   // profiling: an event before each level launch, one after the chunk
+    std::vector<hipEvent_t> &lev_ev = lev_pool.v;
     // launches for levels L .. L + k - 1 (with profiling events)
     auto level_chunk = [&](uint32_t L, uint32_t k) -> cfpq_status {
-        if (prof)
-            while (lev_ev.size() < k + 1) {
-                hipEvent_t e;
-                HIP_TRY(hipEventCreate(&e));
-                lev_ev.push_back(e);
-            }
+        if (prof) HIP_TRY(lev_pool.ensure(k + 1));
         for (uint32_t j = 0; j < k; ++j) {
             const uint32_t l = L + j;
             if (prof) HIP_TRY(hipEventRecord(lev_ev[j], s));
-            HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, stripe, pending, lev, d_u64(T), d_u64(res.NT), nzf,
+            HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, stripe, pending, lev, Tp, d_u64(res.NT), nzf,
                                       tb.is_start, l, lc + l % kCtr, lc + (l + 1) % kCtr, lc + (l + 2) % kCtr,
                                       box_pairs, bytes_ctr, s));
         }
@@ -1404,7 +1451,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         HIP_TRY(launch_fill((uint64_t *)wb_ctr, (uint64_t)nB * kSlotWords, 0, s));
         WritebackArgs w{};
         w.n = n; w.P = P; w.Pn = Pn; w.nB = nB; w.fin_off = tb.fin_off; w.fin = tb.fin;
-        w.T = d_u64(T); w.NT = d_u64(res.NT); w.dNT = nullptr; w.dnt_act = nullptr; w.fresh = fresh;
+        w.T = Tp; w.NT = d_u64(res.NT); w.dNT = nullptr; w.dnt_act = nullptr; w.fresh = fresh;
         w.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
         w.iter = 1; w.ctr = wb_ctr; w.slot_base = 0; w.row_map = scc; w.row_nz = nzf;
         w.state_flags = tb.is_start; w.multi = size;
@@ -1522,7 +1569,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         if ((st = levels(0)) != CFPQ_OK) return st;
         HIP_TRY(hipEventRecord(ev[2], s));
         if ((st = writeback(nullptr, nullptr)) != CFPQ_OK) return st;
-        if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, nzf, d_u64(T), s));
+        if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, nzf, Tp, s));
         HIP_TRY(hipEventRecord(ev[3], s));
     }
     if (!finished) {
