@@ -36,7 +36,16 @@ HBM_PEAK_GBS = 8000.0
 # kernel: fetch x2.0, write x1.0), keyed by (digest of the kernel sources,
 # workload, kernel).  Any change to a kernel source changes the digest, and
 # the figure is reported as null until the counters are taken again.
-PMC_TRAFFIC = {}
+# Taken with `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` passes over
+# the bench commands in profiles/ (k_cond_level: the headline run's 7 queries
+# of 18 productive level launches each; the grammar blocks: every launch of
+# the block's runs).
+PMC_TRAFFIC = {
+    ("e5fcb4b25daa51bb", "rpq_powerlaw_n100000", "k_cond_level"): 107339841,
+    ("e5fcb4b25daa51bb", "samegen_n200000", "k_nt_sparse"): 465594773,
+    ("e5fcb4b25daa51bb", "alias_n20000", "k_nt_dense"): 76426258,
+    ("e5fcb4b25daa51bb", "samegen_n50000", "k_writeback"): 547164536,
+}
 
 
 def source_digest():
@@ -548,7 +557,7 @@ def main():
         elif name == "samegen50k":
             out = block_grammar(args, "samegen", args.grammar_n or 50000, 5, 1, 20000)
         elif name == "samegen200k":
-            out = block_grammar(args, "samegen", args.grammar_n or 200000, 3, 1, 0)
+            out = block_grammar(args, "samegen", args.grammar_n or 200000, 3, 1, 20000)
         elif name == "alias":
             out = block_grammar(args, "alias", args.grammar_n or 20000, 5, 1, 8000)
         elif name == "serving":

@@ -1402,23 +1402,37 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     PooledEvents lev_pool;   // profiling: an event before each level launch, one after the chunk
     std::vector<hipEvent_t> &lev_ev = lev_pool.v;
     // launches for levels L .. L + k - 1 (with profiling events)
+    // Profiling times the chain of level launches with one event before its
+    // first launch and one after its last: a timing event on the stream
+    // costs a drain of the GPU (about 5 us measured between dependent
+    // kernels), so per-launch events would add a fifth to the level time
+    // they measure.  CFPQ_PROFILE_EACH_LAUNCH = 1 brackets every launch.
+#ifndef CFPQ_PROFILE_EACH_LAUNCH
+#define CFPQ_PROFILE_EACH_LAUNCH 0
+#endif
+    const auto lev_end = [](uint32_t k) { return CFPQ_PROFILE_EACH_LAUNCH ? k : 1u; };   // event after the chain
     auto level_chunk = [&](uint32_t L, uint32_t k) -> cfpq_status {
-        if (prof) HIP_TRY(lev_pool.ensure(k + 1));
+        if (prof) HIP_TRY(lev_pool.ensure(lev_end(k) + 1));
         for (uint32_t j = 0; j < k; ++j) {
             const uint32_t l = L + j;
-            if (prof) HIP_TRY(hipEventRecord(lev_ev[j], s));
+            if (prof && (CFPQ_PROFILE_EACH_LAUNCH || j == 0)) HIP_TRY(hipEventRecord(lev_ev[j], s));
             HIP_TRY(launch_cond_level(pg, P, Pn, scc, size, stripe, pending, lev, Tp, d_u64(res.NT), nzf,
                                       tb.is_start, l, lc + l % kCtr, lc + (l + 1) % kCtr, lc + (l + 2) % kCtr,
                                       box_pairs, bytes_ctr, s));
         }
-        if (prof) HIP_TRY(hipEventRecord(lev_ev[k], s));
+        if (prof) HIP_TRY(hipEventRecord(lev_ev[lev_end(k)], s));
         return CFPQ_OK;
     };
     auto level_chunk_times = [&](uint32_t k) -> cfpq_status {
         if (!prof) return CFPQ_OK;
-        for (uint32_t j = 0; j < k; ++j) {
-            float t = 0.f;
-            HIP_TRY(hipEventElapsedTime(&t, lev_ev[j], lev_ev[j + 1]));
+        float t = 0.f;
+        if (CFPQ_PROFILE_EACH_LAUNCH) {
+            for (uint32_t j = 0; j < k; ++j) {
+                HIP_TRY(hipEventElapsedTime(&t, lev_ev[j], lev_ev[j + 1]));
+                res.prof[CFPQ_KERNEL_COND_LEVEL].ms += t;
+            }
+        } else if (k) {
+            HIP_TRY(hipEventElapsedTime(&t, lev_ev[0], lev_ev[lev_end(k)]));
             res.prof[CFPQ_KERNEL_COND_LEVEL].ms += t;
         }
         res.prof[CFPQ_KERNEL_COND_LEVEL].launches += k;
@@ -1490,11 +1504,11 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, best, scc, cc + sl++, rq.cnt + hr % 3, rq.cnt + 3 + hr % 3, s));
         const uint32_t rem = sl++;
         HIP_TRY(launch_color_remove(N, alive, found, cc + rem, s));   // nodes still without a component
-        HIP_TRY(hipEventRecord(ev[1], s));
+        if (prof) HIP_TRY(hipEventRecord(ev[1], s));
         cfpq_status st2 = condense_setup(cc + rem);
         if (st2 != CFPQ_OK) return st2;
         if ((st2 = level_chunk(0, hl)) != CFPQ_OK) return st2;
-        HIP_TRY(hipEventRecord(ev[2], s));
+        if (prof) HIP_TRY(hipEventRecord(ev[2], s));
         if ((st2 = writeback(cc + rem, lc + hl % kCtr)) != CFPQ_OK) return st2;
         HIP_TRY(hipEventRecord(ev[3], s));
         HIP_TRY(hipMemcpyAsync(pc.h, cc, n_out * 8, hipMemcpyDeviceToHost, s));
@@ -1529,7 +1543,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             // colouring, then the condensation from the start (its set-up,
             // levels and write-back were no-ops)
             if ((st2 = colouring()) != CFPQ_OK) return st2;
-            HIP_TRY(hipEventRecord(ev[1], s));
+            if (prof) HIP_TRY(hipEventRecord(ev[1], s));
             HIP_TRY(launch_fill((uint64_t *)lc, kCtr, 0, s));
             if ((st2 = condense_setup(nullptr)) != CFPQ_OK) return st2;
             if ((st2 = levels(0)) != CFPQ_OK) return st2;
@@ -1548,7 +1562,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             }
         }
         if (!finished) {
-            HIP_TRY(hipEventRecord(ev[2], s));
+            if (prof) HIP_TRY(hipEventRecord(ev[2], s));
             if ((st2 = writeback(nullptr, nullptr)) != CFPQ_OK) return st2;
             HIP_TRY(hipEventRecord(ev[3], s));
         }
@@ -1564,10 +1578,10 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         if ((st = next_slot(1)) != CFPQ_OK) return st;
         HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, best, scc, cc + slot++, nullptr, nullptr, s));
         if ((st = colouring()) != CFPQ_OK) return st;
-        HIP_TRY(hipEventRecord(ev[1], s));
+        if (prof) HIP_TRY(hipEventRecord(ev[1], s));
         if ((st = condense_setup(nullptr)) != CFPQ_OK) return st;
         if ((st = levels(0)) != CFPQ_OK) return st;
-        HIP_TRY(hipEventRecord(ev[2], s));
+        if (prof) HIP_TRY(hipEventRecord(ev[2], s));
         if ((st = writeback(nullptr, nullptr)) != CFPQ_OK) return st;
         if (o.keep_blocks) HIP_TRY(launch_cond_expand(N, P, Pn, scc, nzf, Tp, s));
         HIP_TRY(hipEventRecord(ev[3], s));
@@ -1593,11 +1607,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     if (max_iters_hit(o, 2)) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
     float ms = 0.f, ms_scc = 0.f, ms_lv = 0.f, ms_wb = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
-    HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
-    HIP_TRY(hipEventElapsedTime(&ms_lv, ev[1], ev[2]));
-    HIP_TRY(hipEventElapsedTime(&ms_wb, ev[2], ev[3]));
     res.ms = ms;
     if (prof) {
+        // search, levels and write-back events are recorded only when profiling
+        HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
+        HIP_TRY(hipEventElapsedTime(&ms_lv, ev[1], ev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms_wb, ev[2], ev[3]));
         res.prof[CFPQ_KERNEL_COND_SCC].launches += 1;
         res.prof[CFPQ_KERNEL_COND_SCC].ms += ms_scc;
         (void)ms_lv;
