@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # of 18 productive level launches each; the grammar blocks: every launch of
 # the block's runs).
 PMC_TRAFFIC = {
-    ("e5fcb4b25daa51bb", "rpq_powerlaw_n100000", "k_cond_level"): 107339841,
-    ("e5fcb4b25daa51bb", "samegen_n200000", "k_nt_sparse"): 465594773,
-    ("e5fcb4b25daa51bb", "alias_n20000", "k_nt_dense"): 76426258,
-    ("e5fcb4b25daa51bb", "samegen_n50000", "k_writeback"): 547164536,
+    ("802fff81345d4214", "rpq_powerlaw_n100000", "k_cond_level"): 107340623,
+    ("802fff81345d4214", "samegen_n200000", "k_nt_sparse"): 465669615,
+    ("802fff81345d4214", "alias_n20000", "k_nt_dense"): 76425389,
+    ("802fff81345d4214", "samegen_n50000", "k_writeback"): 547168207,
 }
 
 
