@@ -882,6 +882,30 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         dd_rep = (uint32_t *)(dd_hash + rows + slots + slots / 2);
     }
 
+    // The seed's ELL lists of the closure rows, kept per source tile across
+    // iterations: a row's list is rebuilt only if the row gained bits since
+    // the last build (the previous iteration's change bitset).  Closure rows
+    // only grow, so a row found dense stays dense.  (Not with the recomputed
+    // closure, which clears T every iteration.)
+#ifndef CFPQ_SEED_ELL_KEEP
+#define CFPQ_SEED_ELL_KEEP 1
+#endif
+    auto al256b = [](uint64_t x) { return (x + 255) / 256 * 256; };
+    const uint64_t seed_ell_bytes = al256b((ell_pad + (uint64_t)nQ * n * kEll) * 4);
+    const uint64_t seed_tile_bytes = seed_ell_bytes + al256b(dense_words * 8);
+    bool keep_ell = CFPQ_SEED_ELL_KEEP && sparse_nt && !scratch && (uint64_t)groups * seed_tile_bytes <= (8ull << 30);
+    DevBuf seed_buf, chg_prev_buf;
+    if (keep_ell && (!seed_buf.alloc(al, groups * seed_tile_bytes, s) || !chg_prev_buf.alloc(al, aw * 8, s)))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (seed lists)");
+    uint64_t *d_chg_prev = chg_prev_buf.as<uint64_t>();
+    auto seed_tile = [&](uint32_t gi, uint32_t *&cnt, uint32_t *&idx, uint64_t *&dns, uint64_t *&dblk) {
+        uint8_t *b = seed_buf.as<uint8_t>() + (uint64_t)gi * seed_tile_bytes;
+        cnt = (uint32_t *)b;
+        idx = cnt + ell_pad;
+        dns = (uint64_t *)(b + seed_ell_bytes);
+        dblk = dns + (uint64_t)nQ * Pn;
+    };
+
     PinnedCounters pc;
     if (!pc.ensure(4096 * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
     uint32_t slot = 0;
@@ -917,6 +941,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             res.deltas.push_back(0);
             break;
         }
+        if (keep_ell) std::swap(d_chg, d_chg_prev);   // the last iteration's changes pick the lists to rebuild
         HIP_TRY(launch_fill(d_chg, aw, 0, s));   // rows gaining bits in this iteration
         if (scratch && it > 1) {   // forget the closure: only the box-start rows' own bits
             HIP_TRY(launch_fill(d_T, qw, 0, s));
@@ -952,13 +977,22 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
                 // the product rows go to the other frontier buffer and the third
                 // activity bitset, both unused until the first level
                 uint32_t *ell_cnt = ell.as<uint32_t>(), *ell_idx = ell_cnt + ell_pad;
-                HIP_TRY(launch_fill(d_dns, dense_words, 0, s));
+                uint64_t *sdns = d_dns, *sdblk = d_dblk;
+                const uint64_t *rebuild = nullptr;   // null: every row's list
+                if (keep_ell) {
+                    seed_tile(gi, ell_cnt, ell_idx, sdns, sdblk);
+                    if (it > 1) rebuild = d_chg_prev;
+                }
+                if (!rebuild) HIP_TRY(launch_fill(sdns, dense_words, 0, s));
                 HIP_TRY(launch_ell_build_dense(d_T, P, w0, gw, n, tb.nt_src, (uint32_t)p.nt_src.size(), ell_cnt,
-                                               ell_idx, nullptr, Pn, nullptr, d_dns, d_dblk, Pbs, s));
+                                               ell_idx, rebuild, Pn, nullptr, sdns, sdblk, Pbs, s));
                 if ((st = prof_mark3(0, 1)) != CFPQ_OK) return st;
                 HIP_TRY(launch_nt_sparse(a, ell_cnt, ell_idx, Dbuf[1], act[2], grid, s));
                 if ((st = prof_mark3(0, 3)) != CFPQ_OK) return st;
-                if ((st = dense_product(a, Dbuf[1], act[2])) != CFPQ_OK) return st;
+                dargs.dns = sdns; dargs.dblk = sdblk; dargs.ell_idx = ell_idx;
+                st = dense_product(a, Dbuf[1], act[2]);
+                dargs.dns = d_dns; dargs.dblk = d_dblk; dargs.ell_idx = ell.as<uint32_t>() + ell_pad;
+                if (st != CFPQ_OK) return st;
                 a.extra = Dbuf[1]; a.extra_act = act[2];
             } else {
                 if ((st = prof_mark3(0, 1)) != CFPQ_OK) return st;
