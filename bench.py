@@ -272,6 +272,7 @@ def block_brackets(args):
     res["roofline"] = {"bound": "latency",
                        "note": "the working set (<= 128 KiB) fits one CU; one workgroup runs the whole fixpoint, "
                                "so neither HBM nor the matrix cores bound it: us per iteration is the figure"}
+    res["autotuned"] = autotune_report(graph, q)
     if not args.no_cpu:
         tc = time.perf_counter()
         k = 0
@@ -283,6 +284,32 @@ def block_brackets(args):
                                "sample": f"the whole query (worklist over the normal form), {k} runs, "
                                          f"{dt * 1e3:.2f} ms each on 1 thread"}
     return res
+
+
+def autotune_report(graph, q):
+    """What the autotuner picks for this query's class, measured afresh
+    (a cache file of its own, removed afterwards): every candidate's time
+    and the choice."""
+    import tempfile
+    from paper_2103_14688_amd import cfpq, tune
+    names = {cfpq.STRATEGY_FUSED: "fused", cfpq.STRATEGY_LEVELS: "levels", cfpq.STRATEGY_CONDENSED: "condensed",
+             cfpq.STRATEGY_PEREDGE: "peredge"}
+
+    def label(o):
+        parts = [names.get(o.get("strategy"), str(o.get("strategy")))]
+        if "nt_mode" in o:
+            parts.append({cfpq.NT_AUTO: "sparse", cfpq.NT_ROWS: "rows", cfpq.NT_MFMA: "mfma"}[o["nt_mode"]])
+        if o.get("tile_words"):
+            parts.append(f"tile{o['tile_words']}")
+        if o.get("recompute"):
+            parts.append("recomputed")
+        return "/".join(parts)
+
+    with tempfile.TemporaryDirectory() as d:
+        t = tune.Tuner(os.path.join(d, "tune.json"), runs=2)
+        opts, entry = t.tune(graph, q)
+    return {"class": tune.key_of(entry["features"]), "choice": label(opts),
+            "measured_ms": {label(m["options"]): m["ms"] for m in entry["measured"]}}
 
 
 def block_grammar(args, which, n, steps, warmup, cpu_n):
@@ -329,6 +356,8 @@ def block_grammar(args, which, n, steps, warmup, cpu_n):
            "closure": "recomputed each iteration" if args.recompute else "incremental", "nt_mode": args.nt_mode,
            "roofline": roofline(dom.split(" ")[0], prof[dom][0], prof[dom][1], prof[dom][2], f"{which}_n{n}")}
     r.close()
+    if getattr(args, "tune_blocks", True) and n <= 50000:
+        out["autotuned"] = autotune_report(graph, q)
     if cpu_n and not args.no_cpu:
         if which == "samegen":
             gc = synth.hierarchy(cpu_n, seed=synth.BASE_SEED + 3)[0]
