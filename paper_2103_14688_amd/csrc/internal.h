@@ -325,11 +325,18 @@ constexpr uint32_t kCondChunkWords = CFPQ_COND_LANE_WORDS * 64;
 static_assert(kCondChunkWords % CFPQ_COND_VEC == 0, "chunk capacity in whole vectors");
 // equal widths, rounded up to whole vectors (never above the capacity); the
 // count follows from the width, so the last chunk is never empty
+// chunk width rounded to CFPQ_COND_CHUNK_ALIGN words (a multiple of
+// CFPQ_COND_VEC dividing 64, so the rounded width stays within
+// kCondChunkWords)
+#ifndef CFPQ_COND_CHUNK_ALIGN
+#define CFPQ_COND_CHUNK_ALIGN 16
+#endif
+static_assert(CFPQ_COND_CHUNK_ALIGN % CFPQ_COND_VEC == 0 && 64 % CFPQ_COND_CHUNK_ALIGN == 0, "chunk alignment");
 __host__ __device__ inline uint32_t cond_chunk_words(uint32_t Pn) {
     if (Pn == 0) return kCondChunkWords;
     const uint32_t c = (Pn + kCondChunkWords - 1) / kCondChunkWords;
     const uint32_t w = (Pn + c - 1) / c;
-    return (w + CFPQ_COND_VEC - 1) / CFPQ_COND_VEC * CFPQ_COND_VEC;
+    return (w + CFPQ_COND_CHUNK_ALIGN - 1) / CFPQ_COND_CHUNK_ALIGN * CFPQ_COND_CHUNK_ALIGN;
 }
 __host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) {
     const uint32_t w = cond_chunk_words(Pn);
