@@ -113,6 +113,7 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 #define CFPQ_ROW_ALIGN_WORDS 16
 #endif
 constexpr uint32_t kRowAlignWords = CFPQ_ROW_ALIGN_WORDS;
+static_assert(kRowAlignWords % 2 == 0, "rows start on 16-byte boundaries");
 
 // the graph's successor lists on the host, shared by the graph and the
 // results made on it (path extraction reads them after the graph is gone)

@@ -784,6 +784,10 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 #ifndef CFPQ_COND_MIN_WAVES
 #define CFPQ_COND_MIN_WAVES 1
 #endif
+#ifndef CFPQ_COND_ZERO16
+#define CFPQ_COND_ZERO16 1
+#endif
+static_assert(!CFPQ_COND_ZERO16 || CFPQ_COND_CHUNK_ALIGN % 2 == 0, "16-byte stores need chunks on even words");
 __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(ProdGraph g, uint32_t P, uint32_t Pn, const uint32_t *scc,
                                                        const uint32_t *multi, uint32_t *indeg, uint32_t *pending,
                                                        uint32_t *lev, uint64_t *R, uint64_t *NT, uint8_t *nz,
@@ -943,6 +947,25 @@ __global__ __launch_bounds__(kBlock, CFPQ_COND_MIN_WAVES) void k_cond_level(Prod
             for (int q = 0; q < kNS; ++q) {
                 if (!doN[q]) continue;
                 uint64_t *row = off_ptr(ownN[q], R, NT) + pass0;
+#if CFPQ_COND_ZERO16
+                if (!anyN[q]) {
+                    // an empty answer-row chunk (nothing listed, no seed):
+                    // zeros in 16-byte streaming stores (chunks and rows start
+                    // on 16-word boundaries)
+                    for (uint32_t w = 2 * (uint32_t)lane; w < cw; w += 2 * kWave) {
+                        if (w + 1 < cw) {
+                            u64x2_t z;
+                            z.x = 0;
+                            z.y = 0;
+                            __builtin_nontemporal_store(z, reinterpret_cast<u64x2_t *>(row + w));
+                        } else {
+                            store_row_word(row + w, 0ull);
+                        }
+                    }
+                    if (lane == 0) words_w += cw;
+                    continue;
+                }
+#endif
                 unsigned long long pc = 0;
 #pragma unroll
                 for (int kk = 0; kk < kCondPassWords; kk += kCondVec) {
