@@ -197,7 +197,7 @@ def headline(args):
                    "fixpoint_ms_mean": float(np.mean(fix)), "first_query_ms": cold_ms,
                    "tile_words": args.tile_words, "strategy": args.strategy,
                    "level_launches_per_step": lv_n / args.steps,
-                   "component_search_ms_per_step": sum(x[3][1] for x in rows) / args.steps,
+                   "search_and_setup_ms_per_step": sum(x[3][1] for x in rows) / args.steps,
                    "writeback_ms_per_step": sum(x[2][1] for x in rows) / args.steps},
         "roofline": roof, "cpu_baseline": cpu,
     }

@@ -365,7 +365,8 @@ void cfpq_paths_close(cfpq_paths it);
  *     other rows only in their non-empty chunks, a row cut into
  *     ceil(ceil(n/64) / 832) equal chunks) plus 8 bytes per word of
  *     predecessor rows it ORs in;
- *   CFPQ_KERNEL_COND_SCC: the component search (no byte count);
+ *   CFPQ_KERNEL_COND_SCC: the component search and the condensation set-up
+ *     (component in-degrees, links, level-0 roots), no byte count;
  *   CFPQ_KERNEL_NT_MFMA: matrix-core nonterminal products in closure levels;
  *     *bytes receives int8 operations, 2 per multiply-accumulate (65536 per
  *     v_mfma_i32_32x32x32_i8);

@@ -1531,6 +1531,8 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     constexpr uint32_t kSpecBase = kBytesSlot + 2 * kWave;   // past the closure's counters
     const bool spec = ht && hr && hl && hl <= 1024 && (uint64_t)kSpecBase + ht + hr + 2 <= kCtr && !o.keep_blocks;
     bool finished = false;
+    float ms_scc = 0.f, ms_wb = 0.f;         // profiling: search with set-up, write-back
+    bool scc_timed = false, wb_timed = false;   // taken from the level chain's events
     if (spec) {
         uint32_t sl = kSpecBase;
         const uint32_t trim0 = sl;
@@ -1547,20 +1549,25 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, best, scc, cc + sl++, rq.cnt + hr % 3, rq.cnt + 3 + hr % 3, s));
         const uint32_t rem = sl++;
         HIP_TRY(launch_color_remove(N, alive, found, cc + rem, s));   // nodes still without a component
-        if (prof) HIP_TRY(hipEventRecord(ev[1], s));
+        // profiling: the search and the condensation set-up end where the
+        // level chain's first event is, the write-back begins at its last
+        // (no events of their own: each timing event drains the GPU)
         cfpq_status st2 = condense_setup(cc + rem);
         if (st2 != CFPQ_OK) return st2;
         if ((st2 = level_chunk(0, hl)) != CFPQ_OK) return st2;
-        if (prof) HIP_TRY(hipEventRecord(ev[2], s));
         if ((st2 = writeback(cc + rem, lc + hl % kCtr)) != CFPQ_OK) return st2;
         HIP_TRY(hipEventRecord(ev[3], s));
-        HIP_TRY(hipMemcpyAsync(pc.h, cc, n_out * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(pc.h + kSpecBase, cc + kSpecBase, (size_t)(sl - kSpecBase) * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(pc.h + kCtr, lc, (size_t)(hl + 1) * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(pc.h + 2 * kCtr, rq.cnt, 6 * 8, hipMemcpyDeviceToHost, s));
-        if (prof) HIP_TRY(hipMemcpyAsync(pc.h + kBytesSlot, bytes_ctr, 2 * kWave * 8, hipMemcpyDeviceToHost, s));
+        // one read-back of the whole counter area (pc.h mirrors its layout):
+        // answer pairs, write-back and byte counters, the speculative
+        // launches' counters, the level counts and the search frontiers
+        HIP_TRY(hipMemcpyAsync(pc.h, cc, kPinWords * 8, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if ((st2 = level_chunk_times(hl)) != CFPQ_OK) return st2;
+        if (prof) {
+            HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], lev_ev[0]));
+            HIP_TRY(hipEventElapsedTime(&ms_wb, lev_ev[lev_end(hl)], ev[3]));
+            scc_timed = wb_timed = true;   // valid if the query finished here
+        }
         // chain lengths for the next query, as the synchronous chains count them
         uint32_t used = 2 * ht;
         for (uint32_t j = 0; j < ht; ++j)
@@ -1569,7 +1576,8 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
                 break;
             }
         g.hint_trim.store(std::min<uint32_t>(used, 256), std::memory_order_relaxed);
-        const bool searched = (pc.h[2 * kCtr + hr % 3] | pc.h[2 * kCtr + 3 + hr % 3]) == 0;
+        const unsigned long long *fr = pc.h + (rq.cnt - cc);   // frontier sizes
+        const bool searched = (fr[hr % 3] | fr[3 + hr % 3]) == 0;
         if (!searched) {
             // the searches go on from frontier hr; nothing after them ran
             if ((st2 = reach_chain(hr)) != CFPQ_OK) return st2;
@@ -1586,22 +1594,24 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             // colouring, then the condensation from the start (its set-up,
             // levels and write-back were no-ops)
             if ((st2 = colouring()) != CFPQ_OK) return st2;
-            if (prof) HIP_TRY(hipEventRecord(ev[1], s));
             HIP_TRY(launch_fill((uint64_t *)lc, kCtr, 0, s));
             if ((st2 = condense_setup(nullptr)) != CFPQ_OK) return st2;
+            if (prof) HIP_TRY(hipEventRecord(ev[1], s));
+            scc_timed = wb_timed = false;
             if ((st2 = levels(0)) != CFPQ_OK) return st2;
         } else {
             uint32_t z = hl + 1;   // first empty level, if one was launched
             for (uint32_t j = 0; j <= hl; ++j)
-                if (pc.h[kCtr + j] == 0) {
+                if (pc.h[(lc - cc) + j] == 0) {
                     z = j;
                     break;
                 }
             if (z <= hl) {
                 g.hint_levels.store(std::max<uint32_t>(z, 1), std::memory_order_relaxed);
                 finished = true;   // the write-back ran and its counters are read
-            } else if ((st2 = levels(hl)) != CFPQ_OK) {
-                return st2;
+            } else {
+                wb_timed = false;
+                if ((st2 = levels(hl)) != CFPQ_OK) return st2;
             }
         }
         if (!finished) {
@@ -1621,8 +1631,8 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         if ((st = next_slot(1)) != CFPQ_OK) return st;
         HIP_TRY(launch_fwbw_assign(N, alive, fw, bwm, best, scc, cc + slot++, nullptr, nullptr, s));
         if ((st = colouring()) != CFPQ_OK) return st;
-        if (prof) HIP_TRY(hipEventRecord(ev[1], s));
         if ((st = condense_setup(nullptr)) != CFPQ_OK) return st;
+        if (prof) HIP_TRY(hipEventRecord(ev[1], s));
         if ((st = levels(0)) != CFPQ_OK) return st;
         if (prof) HIP_TRY(hipEventRecord(ev[2], s));
         if ((st = writeback(nullptr, nullptr)) != CFPQ_OK) return st;
@@ -1648,17 +1658,16 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     res.deltas.assign({delta, 0});
     res.iterations = 2;
     if (max_iters_hit(o, 2)) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
-    float ms = 0.f, ms_scc = 0.f, ms_lv = 0.f, ms_wb = 0.f;
+    float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[3]));
     res.ms = ms;
     if (prof) {
-        // search, levels and write-back events are recorded only when profiling
-        HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
-        HIP_TRY(hipEventElapsedTime(&ms_lv, ev[1], ev[2]));
-        HIP_TRY(hipEventElapsedTime(&ms_wb, ev[2], ev[3]));
+        // search (with the condensation set-up) and write-back times; the
+        // events are recorded only when profiling
+        if (!scc_timed) HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], ev[1]));
+        if (!wb_timed) HIP_TRY(hipEventElapsedTime(&ms_wb, ev[2], ev[3]));
         res.prof[CFPQ_KERNEL_COND_SCC].launches += 1;
         res.prof[CFPQ_KERNEL_COND_SCC].ms += ms_scc;
-        (void)ms_lv;
         res.prof[CFPQ_KERNEL_COND_LEVEL].bytes += level_bytes;
         res.prof[CFPQ_KERNEL_WRITEBACK].launches += 1;
         res.prof[CFPQ_KERNEL_WRITEBACK].ms += ms_wb;
