@@ -114,6 +114,9 @@ uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
 #endif
 constexpr uint32_t kRowAlignWords = CFPQ_ROW_ALIGN_WORDS;
 static_assert(kRowAlignWords % 2 == 0, "rows start on 16-byte boundaries");
+// rows of at most 8 words keep an 8-word pitch: small graphs (the fused
+// path) would otherwise clear and scan twice the memory
+uint32_t row_pitch(uint32_t Pn) { return round_up(Pn, Pn <= 8 ? 8u : kRowAlignWords); }
 
 // the graph's successor lists on the host, shared by the graph and the
 // results made on it (path extraction reads them after the graph is gone)
@@ -390,7 +393,7 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     Plan p;
     p.n = g.n;
     p.Pn = (g.n + 63) / 64;
-    p.P = round_up(p.Pn, kRowAlignWords);
+    p.P = row_pitch(p.Pn);
     p.nQ = r.n_states;
     p.nB = r.n_boxes;
     p.n_terms = r.n_terms;
@@ -1873,7 +1876,7 @@ cfpq_result_s *new_result(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     res->device = g.device;
     res->n = g.n;
     res->Pn = (g.n + 63) / 64;
-    res->P = round_up(res->Pn, kRowAlignWords);
+    res->P = row_pitch(res->Pn);
     res->nB = r.n_boxes;
     res->nQ = r.n_states;
     res->stream = (hipStream_t)o.stream;

@@ -50,7 +50,8 @@ class Request:
 def footprint(n, n_states, n_boxes):
     """Estimated device bytes of one query: closure rows, two frontiers,
     nonterminal matrices and their deltas (bit-packed, padded rows)."""
-    words = ((n + 63) // 64 + 15) // 16 * 16
+    pn = (n + 63) // 64
+    words = (pn + 7) // 8 * 8 if pn <= 8 else (pn + 15) // 16 * 16
     return 8 * n * words * (3 * n_states + 2 * n_boxes) + (1 << 22)
 
 
