@@ -270,7 +270,7 @@ def block_brackets(args):
     res["batched_1024"] = {"ms_per_batch_wall": dt * 1e3, "queries_per_s": 1024 / dt, "pairs_per_s": pairs / dt,
                            "pairs": pairs}
     res["roofline"] = {"bound": "latency",
-                       "note": "the working set (<= 128 KiB) fits one CU; one workgroup runs the whole fixpoint, "
+                       "note": "one workgroup runs the whole fixpoint with its working set (112 KiB) in LDS, "
                                "so neither HBM nor the matrix cores bound it: us per iteration is the figure"}
     res["autotuned"] = autotune_report(graph, q)
     if not args.no_cpu:

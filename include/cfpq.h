@@ -132,8 +132,10 @@ void cfpq_rsm_destroy(cfpq_rsm r);
  *
  * Options (NULL = defaults):
  *   strategy   : CFPQ_STRATEGY_AUTO, _LEVELS (one launch per closure level,
- *                any size), _FUSED (one workgroup runs the whole fixpoint;
- *                small graphs only, CFPQ_ERR_LIMIT beyond its size limit),
+ *                any size), _FUSED (one workgroup runs the whole fixpoint,
+ *                in LDS when its working set fits the device's per-workgroup
+ *                LDS and keep_blocks is off; small graphs only,
+ *                CFPQ_ERR_LIMIT beyond its size limit),
  *                _CONDENSED (closure through the strongly connected
  *                components of the product graph, each component's row
  *                computed once in topological order; only for RSMs without

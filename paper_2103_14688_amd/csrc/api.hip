@@ -1805,6 +1805,32 @@ void fill_fused(const Plan &p, const cfpq_graph_s &g, const Tables &tb, uint64_t
     q.rank = nullptr;
     q.max_iters = 0;
     q.stats_cap = kStatsCap;
+    q.lds_ok = 1;
+}
+
+// Dynamic LDS words of a fused launch over queries qs[0..k): the largest
+// working set that fits the device (with the odd LDS pitch where that fits
+// too); 0 when none fits.  The device's limit is read once per device.
+uint64_t fused_launch_lds(const FusedQuery *qs, size_t k) {
+    constexpr int kMaxDevices = 64;
+    static std::atomic<uint64_t> limit_plus1[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 0;
+    uint64_t lim = limit_plus1[dev].load(std::memory_order_relaxed);
+    if (!lim) {
+        lim = fused_lds_limit_words() + 1;
+        limit_plus1[dev].store(lim, std::memory_order_relaxed);
+    }
+    const uint64_t limit = lim - 1;
+    uint64_t words = 0;
+    for (size_t i = 0; i < k; ++i) {
+        const FusedQuery &q = qs[i];
+        if (!q.lds_ok) continue;
+        uint64_t need = fused_lds_words(q.n, q.Pn, q.Pn | 1u, q.nQ, q.nB);
+        if (!CFPQ_FUSED_LDS_ODD || need > limit) need = fused_lds_words(q.n, q.Pn, q.Pn, q.nQ, q.nB);
+        if (need <= limit && need > words) words = need;
+    }
+    return words;
 }
 
 cfpq_status prepare_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o,
@@ -1825,6 +1851,7 @@ cfpq_status prepare_fused(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     }
     fill_fused(p, g, job.tb, job.T.as<uint64_t>(), res.NT.as<uint64_t>(), job.work.as<uint64_t>(), job.q);
     job.q.rank = o.keep_rank ? res.rank.as<uint8_t>() : nullptr;
+    job.q.lds_ok = !o.keep_blocks;   // kept closure rows live in T's global buffer
     job.q.max_iters = o.max_iters;
     job.res = &res;
     job.keep_blocks = o.keep_blocks;
@@ -1853,7 +1880,7 @@ cfpq_status run_fused_jobs(std::vector<FusedJob> &jobs, const cfpq_query_opts &o
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipEventRecord(ev0, s));
-    HIP_TRY(launch_fused((const FusedQuery *)base, (uint32_t)qs.size(), next, s));
+    HIP_TRY(launch_fused((const FusedQuery *)base, (uint32_t)qs.size(), next, fused_launch_lds(qs.data(), qs.size()), s));
     HIP_TRY(hipEventRecord(ev1, s));
     HIP_TRY(hipEventSynchronize(ev1));
     float ms = 0.f;
@@ -2106,7 +2133,7 @@ extern "C" cfpq_status cfpq_query_noalloc(cfpq_graph g, cfpq_rsm r, uint32_t box
         HIP_TRY(launch_fill(base, 2, 0, s));
         HIP_TRY(hipMemcpyAsync(b8 + o_tab, im.host.data(), im.host.size(), hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(b8 + o_args, &q, sizeof(q), hipMemcpyHostToDevice, s));
-        HIP_TRY(launch_fused((const FusedQuery *)(b8 + o_args), 1, next, s));
+        HIP_TRY(launch_fused((const FusedQuery *)(b8 + o_args), 1, next, fused_launch_lds(&q, 1), s));
         const uint64_t *rows = q.NT + (uint64_t)box * n * p.P;
         HIP_TRY(launch_transpose(rows, p.P, dst, Pn, n, s));
         HIP_TRY(launch_popcount(rows, n, p.P, Pn, count, s));

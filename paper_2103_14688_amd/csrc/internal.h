@@ -344,6 +344,12 @@ __host__ __device__ inline uint32_t cond_chunks(uint32_t Pn) {
 }
 
 // Fused small-graph fixpoint: one workgroup runs a whole query.
+#ifndef CFPQ_FUSED_LDS
+#define CFPQ_FUSED_LDS 1
+#endif
+#ifndef CFPQ_FUSED_LDS_ODD
+#define CFPQ_FUSED_LDS_ODD 1
+#endif
 struct FusedQuery {
     uint32_t n, P, Pn, n_terms, nQ, nB;
     const uint32_t *goff, *gidx;
@@ -358,9 +364,28 @@ struct FusedQuery {
     uint8_t *rank;
     unsigned long long *stats;     // [0] iterations, [1] status, [2..] per-iteration deltas
     uint32_t max_iters, stats_cap;
+    uint32_t lds_ok;               // the fixpoint may run in LDS (T is not kept)
 };
-hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query,
+// Words of a fused query's working set in LDS: T, D, Dn ([nQ][n] rows),
+// M2^N and A2^N ([nB][n] rows), all at a pitch of `pitch` words, and the
+// activity bitsets (act, actn, tnz: nQ rows, dnt_act: nB rows of Pn words).
+__host__ __device__ inline uint64_t fused_lds_words(uint32_t n, uint32_t Pn, uint32_t pitch, uint32_t nQ,
+                                                    uint32_t nB) {
+    return (3ull * nQ + 2ull * nB) * n * pitch + (3ull * nQ + nB) * Pn;
+}
+// row pitch of a fused query's LDS working set: Pn, made odd (rows of
+// consecutive threads then fall on different banks) where that still fits
+__host__ __device__ inline uint32_t fused_lds_pitch(uint32_t n, uint32_t Pn, uint32_t nQ, uint32_t nB,
+                                                    uint64_t lds_words) {
+    const uint32_t odd = Pn | 1u;
+    return (CFPQ_FUSED_LDS_ODD && fused_lds_words(n, Pn, odd, nQ, nB) <= lds_words) ? odd : Pn;
+}
+// lds_words: the launch's dynamic LDS in words (0: every query in global
+// memory); a query whose working set fits runs there
+hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query, uint64_t lds_words,
                         hipStream_t s);
+// dynamic LDS words a fused launch can take on the current device
+uint64_t fused_lds_limit_words();
 
 // One level of a breadth-first search over the product graph of a box (a
 // frontier vector times the product's Boolean adjacency), recording parent

@@ -1592,26 +1592,89 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     __syncthreads();
 }
 
+// A query whose working set fits the launch's dynamic LDS runs there: its
+// copy of the query record points T, the frontiers, M2^N, A2^N and the
+// activity bitsets into LDS (rows at an LDS pitch of about Pn words), so
+// every row access of the fixpoint is an LDS access instead of an L2 round
+// trip; at the end its M2^N rows go out to the result at the global pitch
+// (pad words zero).  Other queries run on their global buffers.
 __global__ __launch_bounds__(kFusedBlock) void k_fused(const FusedQuery *qs, uint32_t n_queries,
-                                                      uint32_t *next_query) {
+                                                      uint32_t *next_query, uint64_t lds_words) {
+    extern __shared__ uint64_t s_ws[];
     __shared__ uint32_t s_q;
     __shared__ unsigned long long s_cnt;
     __shared__ unsigned long long s_box[kFusedMaxBoxes];
+    __shared__ FusedQuery s_fq;
     for (;;) {
         if (threadIdx.x == 0) s_q = atomicAdd(next_query, 1u);
         __syncthreads();
         const uint32_t qi = s_q;
         __syncthreads();
         if (qi >= n_queries) return;
-        run_fused(qs[qi], &s_cnt, s_box);
+        const FusedQuery &G = qs[qi];
+        const uint32_t n = G.n, Pn = G.Pn, nQ = G.nQ, nB = G.nB;
+        const bool in_lds = G.lds_ok && fused_lds_words(n, Pn, Pn, nQ, nB) <= lds_words;
+        const uint32_t lp = fused_lds_pitch(n, Pn, nQ, nB, lds_words);
+        if (in_lds && threadIdx.x == 0) {
+            s_fq = G;
+            s_fq.P = lp;
+            uint64_t *w = s_ws;   // a generic pointer into LDS
+            s_fq.T = w;
+            w += (uint64_t)nQ * n * lp;
+            s_fq.D = w;
+            w += (uint64_t)nQ * n * lp;
+            s_fq.Dn = w;
+            w += (uint64_t)nQ * n * lp;
+            s_fq.NT = w;
+            w += (uint64_t)nB * n * lp;
+            s_fq.dNT = w;
+            w += (uint64_t)nB * n * lp;
+            s_fq.act = w;
+            w += (uint64_t)nQ * Pn;
+            s_fq.actn = w;
+            w += (uint64_t)nQ * Pn;
+            s_fq.tnz = w;
+            w += (uint64_t)nQ * Pn;
+            s_fq.dnt_act = w;
+        }
+        __syncthreads();
+        run_fused(in_lds ? s_fq : G, &s_cnt, s_box);   // ends with a workgroup barrier
+        if (!in_lds) continue;
+        const uint32_t gp = G.P;
+        uint64_t *out = G.NT;
+        const uint64_t *nt = s_fq.NT;
+        for (uint64_t i = threadIdx.x; i < (uint64_t)nB * n * gp; i += blockDim.x) {
+            const uint64_t row = i / gp;
+            const uint32_t w = (uint32_t)(i - row * gp);
+            out[i] = w < Pn ? nt[row * lp + w] : 0ull;
+        }
+        __syncthreads();
     }
 }
 
-hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query,
+uint64_t fused_lds_limit_words() {
+    if (!CFPQ_FUSED_LDS) return 0;
+    int dev = 0, per_block = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_fused)) != hipSuccess) return 0;
+    const int64_t free_bytes = (int64_t)per_block - (int64_t)fa.sharedSizeBytes;
+    return free_bytes > 0 ? (uint64_t)free_bytes / 8 : 0;
+}
+
+hipError_t launch_fused(const FusedQuery *qs_dev, uint32_t n_queries, uint32_t *next_query, uint64_t lds_words,
                         hipStream_t s) {
     uint32_t grid = n_queries < 1024 ? n_queries : 1024;
     if (!grid) return hipSuccess;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kFusedBlock), 0, s, qs_dev, n_queries, next_query);
+    const size_t lds_bytes = (size_t)lds_words * 8;
+    if (lds_bytes) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fused),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(kFusedBlock), lds_bytes, s, qs_dev, n_queries, next_query,
+                       lds_words);
     return hipGetLastError();
 }
 
