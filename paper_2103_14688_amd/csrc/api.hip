@@ -105,6 +105,7 @@ struct DevBuf {
 };
 
 uint32_t round_up(uint32_t x, uint32_t m) { return (x + m - 1) / m * m; }
+constexpr uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 // row pitch of the device bitsets in 64-bit words: rows start on 128-byte
 // cache-line boundaries (with chunk boundaries on them too, the condensed
 // level kernel's stores cover whole lines: 1.51 -> 1.47 ms per query on the
@@ -150,12 +151,20 @@ struct cfpq_rsm_s {
     std::vector<uint8_t> is_final;
 };
 
+// Device memory that several results share (the answer matrices of one
+// fused batch): freed when the last of them is closed.
+struct SharedDev {
+    Alloc al;
+    DevBuf buf;   // declared after al: freed through it
+};
+
 struct cfpq_result_s {
     int device = 0;
     uint32_t n = 0, P = 0, Pn = 0, nB = 0, nQ = 0;
     hipStream_t stream = nullptr;
     Alloc alloc;
-    DevBuf NT;        // [nB][n][P] transposed nonterminal matrices
+    DevBuf NT;        // [nB][n][P] transposed nonterminal matrices (a view into nt_block when set)
+    std::shared_ptr<SharedDev> nt_block;
     DevBuf T;         // [nQ][n][P] closure rows (keep_blocks)
     DevBuf rank;      // [nB][n][n] u8 (keep_rank)
     DevBuf scratch;   // small device scratch for accessors
@@ -1897,6 +1906,102 @@ cfpq_status run_fused_jobs(std::vector<FusedJob> &jobs, const cfpq_query_opts &o
     return CFPQ_OK;
 }
 
+// Fused queries prepared as one batch (queries that keep neither ranks nor
+// closure blocks): one pinned staging buffer and one host-to-device copy for
+// every table image, query record and the queue head; one work allocation
+// (those, every query's statistics at a common pitch, then T and the work
+// area of each query); one allocation for all answer matrices, which the
+// results share; one read-back of every query's first statistics words.
+constexpr uint32_t kBatchStatWords = 2 + 64;   // iterations, status, first 64 deltas
+cfpq_status run_fused_batch(const std::vector<const cfpq_graph_s *> &gs, const std::vector<const cfpq_rsm_s *> &rs,
+                            const std::vector<cfpq_result_s *> &out, const cfpq_query_opts &o) {
+    const size_t k = out.size();
+    if (!k) return CFPQ_OK;
+    hipStream_t s = (hipStream_t)o.stream;
+    std::vector<Plan> plans(k);
+    std::vector<TableImage> ims(k);
+    std::vector<uint64_t> o_tab(k), o_T(k), o_work(k), o_nt(k);
+    uint64_t at = 0;
+    for (size_t j = 0; j < k; ++j) {
+        plans[j] = make_plan(*gs[j], *rs[j]);
+        pack_tables(plans[j], ims[j]);
+        o_tab[j] = at;
+        at += align256(ims[j].host.size());
+    }
+    const uint64_t o_rec = at, o_head = o_rec + align256(k * sizeof(FusedQuery));
+    const uint64_t staged = o_head + 256;   // these go up in one copy
+    const uint64_t stat_pitch = 2 + kStatsCap;
+    const uint64_t o_stats = staged;
+    uint64_t total = o_stats + align256(k * stat_pitch * 8), nt_total = 0;
+    for (size_t j = 0; j < k; ++j) {
+        const Plan &p = plans[j];
+        const uint64_t qw = (uint64_t)p.nQ * p.n * p.P, bw = (uint64_t)p.nB * p.n * p.P;
+        o_T[j] = total;
+        total += align256(qw * 8);
+        o_work[j] = total;
+        total += align256(fused_work_words(p) * 8);
+        o_nt[j] = nt_total;
+        nt_total += align256(bw * 8);
+    }
+    DevBuf work;
+    auto ntb = std::make_shared<SharedDev>();
+    ntb->al = out[0]->alloc;
+    if (!work.alloc(&out[0]->alloc, total, s) || !ntb->buf.alloc(&ntb->al, nt_total, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (fused batch)");
+    PinnedCounters pin;   // the staging area, later the statistics read-back
+    if (!pin.ensure(std::max<uint64_t>(staged / 8, k * kBatchStatWords)))
+        return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
+    uint8_t *h = reinterpret_cast<uint8_t *>(pin.h);
+    uint8_t *wk = work.as<uint8_t>(), *ntp = ntb->buf.as<uint8_t>();
+    std::vector<FusedQuery> rec(k);
+    for (size_t j = 0; j < k; ++j) {
+        std::memcpy(h + o_tab[j], ims[j].host.data(), ims[j].host.size());
+        Tables tb;
+        bind_tables(ims[j], wk + o_tab[j], tb);
+        fill_fused(plans[j], *gs[j], tb, (uint64_t *)(wk + o_T[j]), (uint64_t *)(ntp + o_nt[j]),
+                   (uint64_t *)(wk + o_work[j]), rec[j]);
+        rec[j].stats = (unsigned long long *)(wk + o_stats) + j * stat_pitch;
+        rec[j].max_iters = o.max_iters;
+    }
+    std::memcpy(h + o_rec, rec.data(), k * sizeof(FusedQuery));
+    std::memset(h + o_head, 0, 256);
+    HIP_TRY(hipMemcpyAsync(wk, h, staged, hipMemcpyHostToDevice, s));
+    PooledEvents evp;
+    HIP_TRY(evp.ensure(2));
+    HIP_TRY(hipEventRecord(evp.v[0], s));
+    HIP_TRY(launch_fused((const FusedQuery *)(wk + o_rec), (uint32_t)k, (uint32_t *)(wk + o_head),
+                         fused_launch_lds(rec.data(), k), s));
+    HIP_TRY(hipEventRecord(evp.v[1], s));
+    // after the staging copy on the same stream: the pinned area is free
+    HIP_TRY(hipMemcpy2DAsync(h, kBatchStatWords * 8, wk + o_stats, stat_pitch * 8, kBatchStatWords * 8, k,
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, evp.v[0], evp.v[1]));
+    const unsigned long long *st = pin.h;
+    for (size_t j = 0; j < k; ++j) {
+        const unsigned long long *sj = st + j * kBatchStatWords;
+        if (sj[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
+        const uint64_t it = sj[0], nd = std::min<uint64_t>(it, kStatsCap);
+        cfpq_result_s &res = *out[j];
+        res.iterations = (uint32_t)it;
+        res.deltas.assign(sj + 2, sj + 2 + std::min<uint64_t>(nd, kBatchStatWords - 2));
+        if (nd > kBatchStatWords - 2) {   // a long fixpoint: the rest of its deltas
+            res.deltas.resize(nd);
+            HIP_TRY(hipMemcpy(res.deltas.data() + (kBatchStatWords - 2), rec[j].stats + kBatchStatWords,
+                              (nd - (kBatchStatWords - 2)) * 8, hipMemcpyDeviceToHost));
+        }
+        res.ms = ms;   // the launch's time, shared by the batch
+        res.NT.release();
+        res.NT.p = ntp + o_nt[j];
+        res.NT.bytes = (size_t)plans[j].nB * plans[j].n * plans[j].P * 8;
+        res.NT.al = nullptr;   // a view: the block is freed with its last result
+        res.NT.s = s;
+        res.nt_block = ntb;
+    }
+    return CFPQ_OK;
+}
+
 cfpq_result_s *new_result(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_query_opts &o) {
     cfpq_result_s *res = new (std::nothrow) cfpq_result_s;
     if (!res) return nullptr;
@@ -1998,7 +2103,9 @@ extern "C" cfpq_status cfpq_query(cfpq_graph g, cfpq_rsm r, const cfpq_query_opt
                 HIP_TRY(hipMemcpyAsync(res->src_mask.p, d_src, (size_t)Pn * 8, hipMemcpyDeviceToDevice, s));
             }
         }
-        if (use_fused(*g, *r, o)) {
+        if (use_fused(*g, *r, o) && !o.keep_rank && !o.keep_blocks) {
+            if ((st = run_fused_batch({g}, {r}, {res.get()}, o)) != CFPQ_OK) return st;
+        } else if (use_fused(*g, *r, o)) {
             std::vector<FusedJob> jobs(1);
             if ((st = prepare_fused(*g, *r, o, *res, jobs[0])) != CFPQ_OK) return st;
             if ((st = run_fused_jobs(jobs, o, &res->alloc)) != CFPQ_OK) return st;
@@ -2030,19 +2137,29 @@ extern "C" cfpq_status cfpq_query_batch(const cfpq_graph *graphs, const cfpq_rsm
     try {
         std::vector<FusedJob> jobs;
         std::vector<uint32_t> big;
+        // fused queries that keep neither ranks nor blocks: one batch
+        const bool batched = !o.keep_rank && !o.keep_blocks;
+        std::vector<const cfpq_graph_s *> bg;
+        std::vector<const cfpq_rsm_s *> br;
+        std::vector<cfpq_result_s *> bres;
         for (uint32_t i = 0; i < k; ++i) {
             if ((st = check_pair(graphs[i], rsms[i])) != CFPQ_OK) return st;
             if ((st = check_opts(*graphs[i], *rsms[i], o)) != CFPQ_OK) return st;
             res[i].reset(new_result(*graphs[i], *rsms[i], o));
             if (!res[i]) return fail(CFPQ_ERR_OOM, "host allocation failed");
-            if (use_fused(*graphs[i], *rsms[i], o)) {
+            if (use_fused(*graphs[i], *rsms[i], o) && batched) {
+                bg.push_back(graphs[i]);
+                br.push_back(rsms[i]);
+                bres.push_back(res[i].get());
+            } else if (use_fused(*graphs[i], *rsms[i], o)) {
                 jobs.emplace_back();
                 if ((st = prepare_fused(*graphs[i], *rsms[i], o, *res[i], jobs.back())) != CFPQ_OK) return st;
             } else {
                 big.push_back(i);
             }
         }
-        if ((st = run_fused_jobs(jobs, o, &res[0]->alloc)) != CFPQ_OK) return st;
+        if ((st = run_fused_batch(bg, br, bres, o)) != CFPQ_OK) return st;
+        if ((st = run_fused_jobs(jobs, o, k ? &res[0]->alloc : nullptr)) != CFPQ_OK) return st;
         jobs.clear();
         for (uint32_t i : big)
             if ((st = run_big(*graphs[i], *rsms[i], o, *res[i])) != CFPQ_OK) return st;
@@ -2086,8 +2203,6 @@ cfpq_status noalloc_scratch(int dev, uint64_t **out) {
     *out = g_noalloc_ptr[dev];
     return CFPQ_OK;
 }
-
-constexpr uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
