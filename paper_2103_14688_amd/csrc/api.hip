@@ -1275,7 +1275,12 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
 #endif
     const bool links = CFPQ_COND_LINKS && (uint64_t)N * kStripes < (1ull << 32);
     const uint64_t link_u32 = links ? (2 + 2 * (uint64_t)kCondLinks) * Nu : 0;
-    const uint64_t o_fnz = o_u32 + al256(Nu * 4 * (9 + kStripes) + link_u32 * 4 + 64);
+    // trimming witnesses: two words per node, zero (none) at the start
+#ifndef CFPQ_TRIM_WITNESS
+#define CFPQ_TRIM_WITNESS 1
+#endif
+    const uint64_t wit_u32 = CFPQ_TRIM_WITNESS ? 2 * Nu : 0;
+    const uint64_t o_fnz = o_u32 + al256(Nu * 4 * (9 + kStripes) + (link_u32 + wit_u32) * 4 + 64);
     const uint64_t o_alive = o_fnz + al256(N64 + nzb + 64);
     const uint64_t o_act = o_alive + al256(N64);
     const uint64_t o_dnt = o_act + al256((uint64_t)nB * Pn * 8);
@@ -1327,6 +1332,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         pg.xin = pg.xout_cnt + Nu;
         pg.xout = pg.xin + (uint64_t)kCondLinks * Nu;
     }
+    if (wit_u32) pg.trim_w = stripe + (uint64_t)kStripes * Nu + link_u32;   // 8-byte aligned (Nu % 4 == 0)
 
     PooledEvents evp;
     HIP_TRY(evp.ensure(4));

@@ -74,6 +74,33 @@ __device__ __forceinline__ bool any_adj(const ProdGraph &g, uint32_t p, F &&test
     return false;
 }
 
+// The first predecessor (successor) x of p that passes test(x), or
+// kNoNode; the same four-edges-per-step walk as any_adj.
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
+template <bool SUCC, class F>
+__device__ __forceinline__ uint32_t first_adj(const ProdGraph &g, uint32_t p, F &&test) {
+    const uint32_t q = p / g.n, v = p - q * g.n;
+    const uint32_t tb = SUCC ? g.out_off[q] : g.in_off[q], te = SUCC ? g.out_off[q + 1] : g.in_off[q + 1];
+    for (uint32_t t = tb; t < te; ++t) {
+        const InTrans tr = SUCC ? g.out_tr[t] : g.in_tr[t];
+        const uint32_t *o = (SUCC ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
+        const uint32_t *idx = SUCC ? g.sidx : g.gidx;
+        const uint32_t b = o[0], e = o[1], base = tr.src * g.n;
+        uint32_t i = b;
+        for (; i + 4 <= e; i += 4) {
+            const uint32_t x0 = base + idx[i], x1 = base + idx[i + 1], x2 = base + idx[i + 2], x3 = base + idx[i + 3];
+            const bool h0 = test(x0), h1 = test(x1), h2 = test(x2), h3 = test(x3);
+            if (h0) return x0;
+            if (h1) return x1;
+            if (h2) return x2;
+            if (h3) return x3;
+        }
+        for (; i < e; ++i)
+            if (test(base + idx[i])) return base + idx[i];
+    }
+    return kNoNode;
+}
+
 template <class F>
 __device__ __forceinline__ void for_succs(const ProdGraph &g, uint32_t p, F &&fn) {
     const uint32_t q = p / g.n, v = p - q * g.n;
@@ -136,8 +163,27 @@ __global__ void k_trim(ProdGraph g, uint8_t *alive, uint32_t *scc, const unsigne
     NODE_LOOP(N) {
         if (!alive[p]) continue;
         auto live_other = [&](uint32_t x) { return x != p && alive[x] != 0; };
-        const bool in = any_adj<false>(g, p, live_other);
-        const bool out = in && any_adj<true>(g, p, live_other);
+        bool in, out;
+        if (g.trim_w) {
+            // the live neighbours the last check found, if still live (a
+            // witness is a neighbour other than p); else walk the edges
+            const uint2 w = reinterpret_cast<const uint2 *>(g.trim_w)[p];
+            in = w.x && alive[w.x - 1];
+            out = w.y && alive[w.y - 1];
+            if (!in) {
+                const uint32_t x = first_adj<false>(g, p, live_other);
+                in = x != kNoNode;
+                if (in) g.trim_w[2 * (uint64_t)p] = x + 1;
+            }
+            if (in && !out) {
+                const uint32_t x = first_adj<true>(g, p, live_other);
+                out = x != kNoNode;
+                if (out) g.trim_w[2 * (uint64_t)p + 1] = x + 1;
+            }
+        } else {
+            in = any_adj<false>(g, p, live_other);
+            out = in && any_adj<true>(g, p, live_other);
+        }
         if (!in || !out) {
             alive[p] = 0;
             scc[p] = p;

@@ -236,6 +236,9 @@ struct ProdGraph {
     // from and stripe counters it retires, with counts (kCondLinks + 1 in
     // xin_cnt: more, walk the edges instead)
     uint32_t *xin_cnt, *xin, *xout_cnt, *xout;
+    // trimming witnesses (null = none kept): per node, 1 + the live
+    // predecessor and 1 + the live successor its last check found (0: none)
+    uint32_t *trim_w;
 };
 constexpr uint32_t kCondLinks = 4;
 
