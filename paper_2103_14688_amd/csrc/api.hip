@@ -396,7 +396,60 @@ struct Plan {
     std::vector<uint32_t> nt_src;        // source states of box-labelled transitions
     std::vector<uint32_t> nt_dst;        // target states of box-labelled transitions
     std::vector<uint32_t> f_box;         // per state: the box of its only box-labelled in-transition, else kNoBox
+    // the transitions inside one strongly connected component of the RSM's
+    // state graph, by target (sin) and by source (sout) state: the only
+    // ones a cycle of the product graph can use
+    std::vector<uint32_t> sin_off, sout_off;
+    std::vector<InTrans> sin_tr, sout_tr;
 };
+
+// strongly connected components of the state graph (Kosaraju, iterative):
+// comp[q] for every state
+std::vector<uint32_t> state_components(const Plan &p) {
+    const uint32_t nQ = p.nQ;
+    std::vector<uint32_t> order, comp(nQ, 0xFFFFFFFFu);
+    std::vector<uint8_t> seen(nQ, 0);
+    std::vector<std::pair<uint32_t, uint32_t>> st;   // (state, next out-transition)
+    for (uint32_t r = 0; r < nQ; ++r) {
+        if (seen[r]) continue;
+        seen[r] = 1;
+        st.push_back({r, p.out_off[r]});
+        while (!st.empty()) {
+            auto &[q, t] = st.back();
+            if (t < p.out_off[q + 1]) {
+                const uint32_t x = p.out_tr[t++].src;   // out_tr: target state in .src
+                if (!seen[x]) {
+                    seen[x] = 1;
+                    st.push_back({x, p.out_off[x]});
+                }
+            } else {
+                order.push_back(q);
+                st.pop_back();
+            }
+        }
+    }
+    uint32_t nc = 0;
+    std::vector<uint32_t> stack;
+    for (size_t i = order.size(); i-- > 0;) {
+        const uint32_t r = order[i];
+        if (comp[r] != 0xFFFFFFFFu) continue;
+        comp[r] = nc;
+        stack.push_back(r);
+        while (!stack.empty()) {
+            const uint32_t q = stack.back();
+            stack.pop_back();
+            for (uint32_t t = p.in_off[q]; t < p.in_off[q + 1]; ++t) {
+                const uint32_t x = p.in_tr[t].src;
+                if (comp[x] == 0xFFFFFFFFu) {
+                    comp[x] = nc;
+                    stack.push_back(x);
+                }
+            }
+        }
+        ++nc;
+    }
+    return comp;
+}
 
 Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
     Plan p;
@@ -464,6 +517,19 @@ Plan make_plan(const cfpq_graph_s &g, const cfpq_rsm_s &r) {
         for (uint32_t q = 0; q < p.nQ; ++q)
             if (calls[q] != 1) p.f_box[q] = kNoBox;
     }
+    {
+        const std::vector<uint32_t> comp = state_components(p);
+        p.sin_off.assign(p.nQ + 1, 0);
+        p.sout_off.assign(p.nQ + 1, 0);
+        for (uint32_t q = 0; q < p.nQ; ++q) {
+            for (uint32_t t = p.in_off[q]; t < p.in_off[q + 1]; ++t)
+                if (comp[p.in_tr[t].src] == comp[q]) p.sin_tr.push_back(p.in_tr[t]);
+            for (uint32_t t = p.out_off[q]; t < p.out_off[q + 1]; ++t)
+                if (comp[p.out_tr[t].src] == comp[q]) p.sout_tr.push_back(p.out_tr[t]);
+            p.sin_off[q + 1] = (uint32_t)p.sin_tr.size();
+            p.sout_off[q + 1] = (uint32_t)p.sout_tr.size();
+        }
+    }
     return p;
 }
 
@@ -472,8 +538,8 @@ struct Tables {
     DevBuf buf;
     uint32_t *in_off = nullptr, *starts = nullptr, *fin_off = nullptr, *fin = nullptr,
              *eps = nullptr, *out_off = nullptr, *is_start = nullptr, *nt_src = nullptr, *nt_dst = nullptr,
-             *f_box = nullptr;
-    InTrans *in_tr = nullptr, *out_tr = nullptr;
+             *f_box = nullptr, *sin_off = nullptr, *sout_off = nullptr;
+    InTrans *in_tr = nullptr, *out_tr = nullptr, *sin_tr = nullptr, *sout_tr = nullptr;
     uint8_t *nullable = nullptr, *box_used = nullptr;
 };
 
@@ -482,7 +548,7 @@ struct Tables {
 struct TableImage {
     std::vector<uint8_t> host;
     size_t in_off, in_tr, starts, fin_off, fin, eps, nullable, box_used, out_off, out_tr, is_start, nt_src, nt_dst,
-        f_box;
+        f_box, sin_off, sin_tr, sout_off, sout_tr;
 };
 
 void pack_tables(const Plan &p, TableImage &im) {
@@ -508,6 +574,10 @@ void pack_tables(const Plan &p, TableImage &im) {
     im.nt_src = put(p.nt_src.data(), p.nt_src.size() * 4);
     im.nt_dst = put(p.nt_dst.data(), p.nt_dst.size() * 4);
     im.f_box = put(p.f_box.data(), p.f_box.size() * 4);
+    im.sin_off = put(p.sin_off.data(), p.sin_off.size() * 4);
+    im.sin_tr = put(p.sin_tr.data(), p.sin_tr.size() * sizeof(InTrans));
+    im.sout_off = put(p.sout_off.data(), p.sout_off.size() * 4);
+    im.sout_tr = put(p.sout_tr.data(), p.sout_tr.size() * sizeof(InTrans));
 }
 
 // table pointers into a device copy of the image at b
@@ -526,6 +596,10 @@ void bind_tables(const TableImage &im, uint8_t *b, Tables &t) {
     t.nt_src = (uint32_t *)(b + im.nt_src);
     t.nt_dst = (uint32_t *)(b + im.nt_dst);
     t.f_box = (uint32_t *)(b + im.f_box);
+    t.sin_off = (uint32_t *)(b + im.sin_off);
+    t.sin_tr = (InTrans *)(b + im.sin_tr);
+    t.sout_off = (uint32_t *)(b + im.sout_off);
+    t.sout_tr = (InTrans *)(b + im.sout_tr);
 }
 
 cfpq_status upload_tables(const Plan &p, const Alloc *al, hipStream_t s, Tables &t) {
@@ -1325,6 +1399,14 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     pg.goff = g.off.as<uint32_t>(); pg.gidx = g.idx.as<uint32_t>();
     pg.soff = g.soff.as<uint32_t>(); pg.sidx = g.sidx.as<uint32_t>();
     pg.in_off = tb.in_off; pg.in_tr = tb.in_tr; pg.out_off = tb.out_off; pg.out_tr = tb.out_tr;
+#ifndef CFPQ_SEARCH_INTRA
+#define CFPQ_SEARCH_INTRA 1
+#endif
+    if (CFPQ_SEARCH_INTRA) {
+        pg.sin_off = tb.sin_off; pg.sin_tr = tb.sin_tr; pg.sout_off = tb.sout_off; pg.sout_tr = tb.sout_tr;
+    } else {
+        pg.sin_off = tb.in_off; pg.sin_tr = tb.in_tr; pg.sout_off = tb.out_off; pg.sout_tr = tb.out_tr;
+    }
     pg.src_mask = res.src_mask.as<uint64_t>();
     if (links) {
         pg.xin_cnt = stripe + (uint64_t)kStripes * Nu;

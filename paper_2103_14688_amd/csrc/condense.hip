@@ -113,6 +113,17 @@ __device__ __forceinline__ void for_succs(const ProdGraph &g, uint32_t p, F &&fn
     }
 }
 
+// g with the component search's transitions (those inside one component
+// of the state graph) in place of all of them
+__device__ __forceinline__ ProdGraph search_view(const ProdGraph &g) {
+    ProdGraph s = g;
+    s.in_off = g.sin_off;
+    s.in_tr = g.sin_tr;
+    s.out_off = g.sout_off;
+    s.out_tr = g.sout_tr;
+    return s;
+}
+
 #define NODE_LOOP(N)                                                                        \
     for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < (N); p += gridDim.x * blockDim.x)
 
@@ -155,9 +166,12 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
 // ----------------------------------------------------------------------------
 // component search
 // ----------------------------------------------------------------------------
-__global__ void k_trim(ProdGraph g, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
+__global__ void k_trim(ProdGraph g_all, uint8_t *alive, uint32_t *scc, const unsigned long long *prev,
                        unsigned long long *ctr) {
     if (prev && *prev == 0) return;  // the previous sweep removed nothing
+    // a node without a live predecessor or successor over the search's
+    // transitions lies on no cycle of live nodes
+    const ProdGraph g = search_view(g_all);
     const uint32_t N = g.nQ * g.n;
     unsigned long long c = 0;
     NODE_LOOP(N) {
@@ -193,7 +207,8 @@ __global__ void k_trim(ProdGraph g, uint8_t *alive, uint32_t *scc, const unsigne
     count_add(ctr, c);
 }
 
-__global__ void k_pivot(ProdGraph g, const uint8_t *alive, unsigned long long *best) {
+__global__ void k_pivot(ProdGraph g_all, const uint8_t *alive, unsigned long long *best) {
+    const ProdGraph g = search_view(g_all);   // degrees over the search's transitions
     const uint32_t N = g.nQ * g.n;
     unsigned long long mine = 0;
     NODE_LOOP(N) {
@@ -273,8 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
             const uint32_t y = cur[base + lane];
             const uint32_t q = y / g.n;
             v = y - q * g.n;
-            tb = fwd ? g.out_off[q] : g.in_off[q];
-            te = fwd ? g.out_off[q + 1] : g.in_off[q + 1];
+            tb = fwd ? g.sout_off[q] : g.sin_off[q];
+            te = fwd ? g.sout_off[q + 1] : g.sin_off[q + 1];
         }
         // claimed nodes gather in s_out and go to the next frontier with one
         // atomic on its size per kReachStage - kWave of them
@@ -295,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
             uint32_t b = 0, e = 0, sb = 0;
             if (tb + k < te) {
                 // in_tr: (source state, label); out_tr: (target state, label)
-                const InTrans tr = fwd ? g.out_tr[tb + k] : g.in_tr[tb + k];
+                const InTrans tr = fwd ? g.sout_tr[tb + k] : g.sin_tr[tb + k];
                 const uint32_t *o = (fwd ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
                 b = o[0];
                 e = o[1];

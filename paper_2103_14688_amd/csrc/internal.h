@@ -230,6 +230,11 @@ struct ProdGraph {
     const uint32_t *in_off, *out_off;
     const InTrans *in_tr;          // per target state: (source state, label)
     const InTrans *out_tr;         // per source state: (target state in .src, label)
+    // the component search's transitions: those inside one strongly
+    // connected component of the state graph (a cycle of the product graph
+    // projects onto a cycle of states, so it uses no other), same layout
+    const uint32_t *sin_off, *sout_off;
+    const InTrans *sin_tr, *sout_tr;
     const uint64_t *src_mask;      // sources searched ([ceil(n/64)] bits), null = all
     // condensation links (written by k_cond_count, read by the level kernel;
     // null = not kept): per node up to kCondLinks components it is entered
