@@ -244,6 +244,10 @@ __global__ void k_pivot(ProdGraph g_all, const uint8_t *alive, unsigned long lon
 }
 
 constexpr uint32_t kReachStage = 256;   // claimed nodes staged per wavefront before an append
+#ifndef CFPQ_REACH_PAIR
+#define CFPQ_REACH_PAIR 2
+#endif
+static_assert(CFPQ_REACH_PAIR == 1 || CFPQ_REACH_PAIR == 2, "one or two transitions per expansion step");
 static_assert(kReachStage >= kWave, "a step's claims fit the staging buffer");
 
 // Forward and backward reachability from the pivot inside the live nodes,
@@ -305,18 +309,30 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
             claimed += lane == 0 ? staged : 0u;
             staged = 0;
         };
+        // CFPQ_REACH_PAIR transitions per step (1 or 2): their edge ranges go
+        // through one scan and one expansion, so the edges of both are in
+        // flight together
+        constexpr uint32_t kTP = CFPQ_REACH_PAIR;
         const uint32_t ntr = wave_max_u32(te - tb);
-        for (uint32_t k = 0; k < ntr; ++k) {
-            uint32_t b = 0, e = 0, sb = 0;
-            if (tb + k < te) {
-                // in_tr: (source state, label); out_tr: (target state, label)
-                const InTrans tr = fwd ? g.sout_tr[tb + k] : g.sin_tr[tb + k];
-                const uint32_t *o = (fwd ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
-                b = o[0];
-                e = o[1];
-                sb = tr.src * g.n;
+        for (uint32_t k = 0; k < ntr; k += kTP) {
+            uint32_t b[kTP], len[kTP], sb[kTP];
+            uint32_t cnt_all = 0;
+#pragma unroll
+            for (uint32_t h = 0; h < kTP; ++h) {
+                b[h] = 0;
+                len[h] = 0;
+                sb[h] = 0;
+                if (tb + k + h < te) {
+                    // in_tr: (source state, label); out_tr: (target state, label)
+                    const InTrans tr = fwd ? g.sout_tr[tb + k + h] : g.sin_tr[tb + k + h];
+                    const uint32_t *o = (fwd ? g.soff : g.goff) + (uint64_t)tr.sym * (g.n + 1) + v;
+                    b[h] = o[0];
+                    len[h] = o[1] - o[0];
+                    sb[h] = tr.src * g.n;
+                }
+                cnt_all += len[h];
             }
-            const uint32_t incl = wave_incl_scan(e - b);
+            const uint32_t incl = wave_incl_scan(cnt_all);
             const uint32_t total = shfl_u32(incl, kWave - 1);
             if (total == 0) continue;
             s_scan[wib][lane] = incl;
@@ -329,12 +345,22 @@ __global__ __launch_bounds__(kBlock) void k_reach(ProdGraph g, const uint8_t *al
                     if (s_scan[wib][mid] > f) hi = mid;
                     else lo = mid + 1;
                 }
-                const uint32_t bj = shfl_u32(b, (int)lo), sbj = shfl_u32(sb, (int)lo);
                 const uint32_t startj = lo ? s_scan[wib][lo - 1] : 0u;
+                uint32_t off = f - startj, bj = shfl_u32(b[0], (int)lo), sbj = shfl_u32(sb[0], (int)lo);
+                if constexpr (kTP == 2) {
+                    // past the owner's first range: its second
+                    const uint32_t l0 = shfl_u32(len[0], (int)lo), b1 = shfl_u32(b[1], (int)lo),
+                                   sb1 = shfl_u32(sb[1], (int)lo);
+                    if (off >= l0) {
+                        off -= l0;
+                        bj = b1;
+                        sbj = sb1;
+                    }
+                }
                 uint32_t x = 0;
                 bool got = false;
                 if (f < total) {
-                    x = sbj + idx[bj + (f - startj)];
+                    x = sbj + idx[bj + off];
                     got = alive[x] && !mark[x] && atomicExch(&mark[x], 1u) == 0u;
                 }
                 const uint64_t m = __ballot(got);

@@ -250,6 +250,28 @@ def test_batch_alone_vs_mix():
         assert res.stats()[:2] == alone.stats()[:2]
 
 
+def test_fused_batch_lds_and_global_queries():
+    # one fused launch whose small queries run in LDS and whose larger ones
+    # (past the per-workgroup LDS) run on their global buffers; the answer
+    # matrices share one block, released here out of order
+    rng = np.random.default_rng(91)
+    labels = ["a", "b", "c", "d"]
+    graphs, queries, wants = [], [], []
+    for i, n in enumerate([64, 256, 700, 1500, 256, 97]):
+        g = synth.powerlaw(n, labels=tuple(labels), mean_deg=3.0, seed=300 + i)
+        text = synth.random_cfg(rng, labels) if i % 2 == 0 else "S -> a S b | a b"
+        graphs.append(cfpq.Graph.from_synth(g))
+        queries.append(cfpq.Query(rsm_mod.from_grammar(text, labels)))
+        wants.append(H.oracle_grammar(g, text)["N0" if i % 2 == 0 else "S"][1])
+    mix = cfpq.query_batch(graphs, queries, strategy=cfpq.STRATEGY_FUSED)
+    for j in (3, 0, 5, 1, 4, 2):
+        assert np.array_equal(mix[j].bitmap(0), wants[j]), j
+        alone = cfpq.query(graphs[j], queries[j], strategy=cfpq.STRATEGY_FUSED)
+        assert mix[j].stats()[:2] == alone.stats()[:2]
+        alone.close()
+        mix[j].close()
+
+
 # ---------------------------------------------------------------------------
 # full bench size: sampled source rows against the oracle's per-source BFS
 # ---------------------------------------------------------------------------
