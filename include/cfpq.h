@@ -365,7 +365,7 @@ void cfpq_paths_close(cfpq_paths it);
  *   CFPQ_KERNEL_COND_LEVEL: one topological level of the component graph,
  *     8 bytes per word of component rows it writes (answer rows in full,
  *     other rows only in their non-empty chunks, a row cut into
- *     ceil(ceil(n/64) / 832) equal chunks) plus 8 bytes per word of
+ *     ceil(ceil(n/64) / 576) equal chunks) plus 8 bytes per word of
  *     predecessor rows it ORs in;
  *   CFPQ_KERNEL_COND_SCC: the component search and the condensation set-up
  *     (component in-degrees, links, level-0 roots), no byte count;

@@ -868,8 +868,10 @@ __device__ void level_node_wave(const ProdGraph &g, uint32_t P, uint32_t Pn, con
 //   C. (first chunk only) edge-parallel over the out-edges: retire the
 //      in-degree stripes of successor components and release them into
 //      level L + 1.
+// at least four wavefronts per SIMD: the kernel is held to 128 VGPRs, so all
+// CFPQ_COND_BLOCKS_PER_CU = 4 workgroups of 4 wavefronts fit a compute unit
 #ifndef CFPQ_COND_MIN_WAVES
-#define CFPQ_COND_MIN_WAVES 1
+#define CFPQ_COND_MIN_WAVES 4
 #endif
 #ifndef CFPQ_COND_ZERO16
 #define CFPQ_COND_ZERO16 1

@@ -309,9 +309,12 @@ hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_
 // A component row is cut into cond_chunks(Pn) equal chunks of at most
 // kCondChunkWords words, each with its own non-empty flag: at most
 // CFPQ_COND_LANE_WORDS words per lane of a wavefront (a compile-time tuning
-// parameter, at most 16; with one node per step 13 measured fastest, ahead
-// of 8, 9 and 16: equal chunks avoid a short last chunk that costs a whole
-// work item, and fewer chunks repeat the predecessor listing less often)
+// parameter, at most 16).  With the level kernel held to 128 VGPRs (four
+// wavefronts per SIMD, CFPQ_COND_MIN_WAVES) 9 words measured fastest (three
+// chunks at n = 10^5: 43.2 us per level launch, against 45.0 with 10, 45.1
+// with 8 and 44.9 with 13 words uncapped, which takes 153 VGPRs and leaves
+// room for three wavefronts per SIMD); 13 words under the cap spill.  Equal
+// chunks avoid a short last chunk that costs a whole work item.
 // The row phase moves CFPQ_COND_VEC words per lane access (1: 8-byte, 2:
 // 16-byte loads and stores; with 2, chunks hold whole pairs of words, so a
 // chunk starts 16-byte aligned, rows being 64-byte aligned).  A compile-time
@@ -324,7 +327,7 @@ hipError_t launch_cond_expand(uint32_t N, uint32_t P, uint32_t Pn, const uint32_
 #if CFPQ_COND_VEC == 2
 #define CFPQ_COND_LANE_WORDS 14
 #else
-#define CFPQ_COND_LANE_WORDS 13
+#define CFPQ_COND_LANE_WORDS 9
 #endif
 #endif
 static_assert(CFPQ_COND_VEC == 1 || CFPQ_COND_VEC == 2, "8- or 16-byte row accesses");

@@ -299,10 +299,11 @@ def test_rpq_bench_size_sampled_rows(strategy):
     assert np.array_equal(again.bitmap(0)[srcs], want)
 
 
-@pytest.mark.parametrize("n", [36865, 74000, 110000])
+@pytest.mark.parametrize("n", [30000, 36865, 74000, 120000])
 def test_rpq_sampled_rows_uneven_chunks(n):
-    # component rows of 577, 1157 and 1719 words: one, two and three equal
-    # chunks of a width that is not a multiple of the wavefront's 64 words
+    # component rows of 469, 577, 1157 and 1875 words: one, two, three and
+    # four chunks (at most 576 words each, widths rounded to 16 words, a
+    # shorter last chunk), none a multiple of the wavefront's 64 words
     import oracle
     g = synth.powerlaw(n, seed=synth.BASE_SEED + 5)
     R = rsm_mod.from_regex(synth.RPQ_C2, g.labels)
