@@ -106,6 +106,18 @@ __global__ void k_fill_u8(uint8_t *p, uint64_t bytes) {
         p[i] = 0;
 }
 
+// minimum wavefronts per SIMD the closure kernels are compiled for (their
+// VGPR budget: 512 / waves); 1 leaves the compiler's choice
+#ifndef CFPQ_NT_SPARSE_MIN_WAVES
+#define CFPQ_NT_SPARSE_MIN_WAVES 1
+#endif
+#ifndef CFPQ_GATHER_MIN_WAVES
+#define CFPQ_GATHER_MIN_WAVES 1
+#endif
+#ifndef CFPQ_WB_MIN_WAVES
+#define CFPQ_WB_MIN_WAVES 1
+#endif
+
 static uint32_t grid_for(uint64_t items, uint32_t block = kBlock, uint32_t cap = 8192) {
     uint64_t g = (items + block - 1) / block;
     if (g == 0) g = 1;
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_ell_build(const uint64_t *rows, uint
 // row v; levels: all of M2^N) of the live source row (s, x): listed rows bit
 // by bit into an LDS accumulator of gw words, dense rows whole into
 // registers; the result goes to extra[(f, v)]
-__global__ __launch_bounds__(kBlock) void k_nt_sparse(GatherArgs a, const uint32_t *ell_cnt,
+__global__ __launch_bounds__(kBlock, CFPQ_NT_SPARSE_MIN_WAVES) void k_nt_sparse(GatherArgs a, const uint32_t *ell_cnt,
                                                        const uint32_t *ell_idx, uint64_t *extra,
                                                        uint64_t *extra_act) {
     if (a.slot_prev != kNoSlot && a.ctr[(uint64_t)a.slot_prev * kSlotWords] == 0) return;  // frontier ran dry
@@ -917,7 +929,7 @@ hipError_t launch_nt_mfma(const MfmaArgs &a, hipStream_t s) {
 }
 
 template <bool SEED>
-__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+__global__ __launch_bounds__(kBlock, CFPQ_GATHER_MIN_WAVES) void k_gather(GatherArgs a) {
     if (a.slot_prev != kNoSlot && a.ctr[(uint64_t)a.slot_prev * kSlotWords] == 0) return;  // frontier ran dry
     const uint64_t gtid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t gthreads = (uint64_t)gridDim.x * blockDim.x;
@@ -1016,7 +1028,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
 
 constexpr uint32_t kWbLdsBoxes = 64;   // boxes whose new-edge counts gather in LDS first
 
-__global__ __launch_bounds__(kBlock) void k_writeback(WritebackArgs a) {
+__global__ __launch_bounds__(kBlock, CFPQ_WB_MIN_WAVES) void k_writeback(WritebackArgs a) {
     if ((a.skip_if[0] && *a.skip_if[0]) || (a.skip_if[1] && *a.skip_if[1])) return;
     // new edges per box: summed per workgroup in LDS (rows of one box meet
     // on one counter), flushed with one atomic per box and workgroup
