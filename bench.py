@@ -39,12 +39,12 @@ HBM_PEAK_GBS = 8000.0
 # Taken with `rocprofv3 --pmc FETCH_SIZE` and `--pmc WRITE_SIZE` passes over
 # the bench commands in profiles/ (k_cond_level: the headline run's 7 queries
 # of 18 productive level launches each; the grammar blocks: every launch of
-# the block's runs).
+# the block's runs, without the autotuner's).
 PMC_TRAFFIC = {
-    ("802fff81345d4214", "rpq_powerlaw_n100000", "k_cond_level"): 107340623,
-    ("802fff81345d4214", "samegen_n200000", "k_nt_sparse"): 465669615,
-    ("802fff81345d4214", "alias_n20000", "k_nt_dense"): 76425389,
-    ("802fff81345d4214", "samegen_n50000", "k_writeback"): 547168207,
+    ("8b4c23754ec5e441", "rpq_powerlaw_n100000", "k_cond_level"): 101206877,
+    ("8b4c23754ec5e441", "samegen_n200000", "k_nt_sparse"): 464179610,
+    ("8b4c23754ec5e441", "alias_n20000", "k_nt_dense"): 76430029,
+    ("8b4c23754ec5e441", "samegen_n50000", "k_writeback"): 547175424,
 }
 
 
@@ -272,7 +272,8 @@ def block_brackets(args):
     res["roofline"] = {"bound": "latency",
                        "note": "one workgroup runs the whole fixpoint with its working set (112 KiB) in LDS, "
                                "so neither HBM nor the matrix cores bound it: us per iteration is the figure"}
-    res["autotuned"] = autotune_report(graph, q)
+    if not args.no_autotune:
+        res["autotuned"] = autotune_report(graph, q)
     if not args.no_cpu:
         tc = time.perf_counter()
         k = 0
@@ -356,7 +357,7 @@ def block_grammar(args, which, n, steps, warmup, cpu_n):
            "closure": "recomputed each iteration" if args.recompute else "incremental", "nt_mode": args.nt_mode,
            "roofline": roofline(dom.split(" ")[0], prof[dom][0], prof[dom][1], prof[dom][2], f"{which}_n{n}")}
     r.close()
-    if getattr(args, "tune_blocks", True) and n <= 50000:
+    if not args.no_autotune and n <= 50000:
         out["autotuned"] = autotune_report(graph, q)
     if cpu_n and not args.no_cpu:
         if which == "samegen":
@@ -540,6 +541,8 @@ def main():
                     help="grammar workloads: recompute the closure from scratch every iteration")
     ap.add_argument("--cpu-sources", type=int, default=20000, help="headline oracle sample (sources)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="blocks skip the autotuner report (profiling runs: only the block's own queries)")
     ap.add_argument("--blocks", default=",".join(BLOCKS),
                     help="workload blocks to add to the line (comma list of " + ",".join(BLOCKS) + ", or none)")
     ap.add_argument("--only", choices=BLOCKS + ["paths", "peredge"], default=None,
