@@ -559,8 +559,8 @@ def main():
                          "FETCH_SIZE/WRITE_SIZE scale factor) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): this build has no multi-GPU path; "
-              f"the sharding is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU path "
+              f"(one process drives one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch
