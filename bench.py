@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # of 18 productive level launches each; the grammar blocks: every launch of
 # the block's runs, without the autotuner's).
 PMC_TRAFFIC = {
-    ("8b4c23754ec5e441", "rpq_powerlaw_n100000", "k_cond_level"): 101206877,
-    ("8b4c23754ec5e441", "samegen_n200000", "k_nt_sparse"): 464179610,
-    ("8b4c23754ec5e441", "alias_n20000", "k_nt_dense"): 76430029,
-    ("8b4c23754ec5e441", "samegen_n50000", "k_writeback"): 547175424,
+    ("da10658b8768e21e", "rpq_powerlaw_n100000", "k_cond_level"): 101207771,
+    ("da10658b8768e21e", "samegen_n200000", "k_nt_sparse"): 499250483,
+    ("da10658b8768e21e", "alias_n20000", "k_nt_dense"): 76432077,
+    ("da10658b8768e21e", "samegen_n50000", "k_writeback"): 547175424,
 }
 
 

@@ -762,8 +762,9 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         G = std::min<uint32_t>(o.tile_words, Pn);
     } else {
         // with box-labelled transitions, narrower tiles also keep more
-        // frontier rows within an ELL list (fewer whole-row ORs): measured
-        // best near 800-1600 words, so tiles of at most kTileCapWords, equal
+        // frontier rows within an ELL list (fewer whole-row ORs), wider ones
+        // run fewer passes: measured best near 1600 words, so tiles of at most
+        // kTileCapWords, equal
         if (!p.nt_src.empty() && o.nt_mode != CFPQ_NT_ROWS) G = std::min<uint32_t>(G, kTileCapWords);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {

@@ -111,8 +111,10 @@ static_assert(kEll >= 2, "a dense row's list holds its 64-bit block mask");
 // (narrower rows are ORed whole at no greater cost)
 constexpr uint32_t kLevelSparseMinWords = 16;
 // automatic source tiles of queries with box-labelled transitions: at most
-// this many words (see run_levels)
-constexpr uint32_t kTileCapWords = 1200;
+// this many words (see run_levels; same generation n = 2e5: two tiles of
+// 1563 words 760 ms, three of 1042 862 ms, one 794 ms; memory alias
+// n = 1e5: one tile 10.71 s, two 10.47 s)
+constexpr uint32_t kTileCapWords = 1600;
 constexpr uint32_t kSparseMaxWords = 4096;     // LDS row accumulator limit (words per wavefront)
 
 struct WritebackArgs {
