@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <array>
 #include <cstdio>
 #include <cstring>
@@ -728,6 +729,23 @@ struct PooledEvents {
 
 uint64_t *d_u64(const DevBuf &b) { return b.as<uint64_t>(); }
 
+// Wait for the stream's work: poll it for up to CFPQ_SPIN_US microseconds
+// (a query's last read-back is usually done within that), then block.
+#ifndef CFPQ_SPIN_US
+#define CFPQ_SPIN_US 2000
+#endif
+hipError_t wait_stream(hipStream_t s) {
+    if (CFPQ_SPIN_US > 0) {
+        const auto t0 = std::chrono::steady_clock::now();
+        for (;;) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e != hipErrorNotReady) return e;
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(CFPQ_SPIN_US)) break;
+        }
+    }
+    return hipStreamSynchronize(s);
+}
+
 bool max_iters_hit(const cfpq_query_opts &o, uint32_t it) { return o.max_iters && it > o.max_iters; }
 
 uint32_t gather_grid(uint64_t rows) {
@@ -1019,7 +1037,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         if (!pc.ensure((size_t)k * kSlotWords)) return fail(CFPQ_ERR_OOM, "pinned host allocation failed");
         HIP_TRY(hipMemcpyAsync(pc.h, d_ctr + (uint64_t)first * kSlotWords, (size_t)k * kSlotWords * 8,
                                hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_stream(s));
         return CFPQ_OK;
     };
 
@@ -1434,7 +1452,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
     };
     auto read = [&](uint32_t first, uint32_t k) -> cfpq_status {
         HIP_TRY(hipMemcpyAsync(pc.h, cc + first, (size_t)k * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_stream(s));
         return CFPQ_OK;
     };
     // run launch(i, prev, cur) as a chain until a launch counts zero: chunks of
@@ -1590,7 +1608,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
             cfpq_status st2 = level_chunk(L, k);
             if (st2 != CFPQ_OK) return st2;
             HIP_TRY(hipMemcpyAsync(pc.h, lc, (size_t)kCtr * 8, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(wait_stream(s));
             if ((st2 = level_chunk_times(k)) != CFPQ_OK) return st2;
             for (uint32_t j = 0; j <= k; ++j)
                 if (pc.h[(L + j) % kCtr] == 0) {
@@ -1662,7 +1680,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         // answer pairs, write-back and byte counters, the speculative
         // launches' counters, the level counts and the search frontiers
         HIP_TRY(hipMemcpyAsync(pc.h, cc, kPinWords * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_stream(s));
         if ((st2 = level_chunk_times(hl)) != CFPQ_OK) return st2;
         if (prof) {
             HIP_TRY(hipEventElapsedTime(&ms_scc, ev[0], lev_ev[0]));
@@ -1745,7 +1763,7 @@ cfpq_status run_condensed(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq
         // kernel's byte counters in one read
         HIP_TRY(hipMemcpyAsync(pc.h, cc, n_out * 8, hipMemcpyDeviceToHost, s));
         if (prof) HIP_TRY(hipMemcpyAsync(pc.h + kBytesSlot, bytes_ctr, 2 * kWave * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_stream(s));
     }
     uint64_t delta = 0;
     for (uint32_t b = 0; b < nB; ++b) {
@@ -1846,7 +1864,7 @@ cfpq_status run_peredge(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_q
                                  res.NT.as<uint64_t>() + (uint64_t)b * n * p.P, p.P, n, s));
     std::vector<unsigned long long> h(3 + kStatsCap);
     HIP_TRY(hipMemcpyAsync(h.data(), stats.p, h.size() * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(wait_stream(s));
     if (h[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop within max_iters iterations");
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
@@ -2064,7 +2082,7 @@ cfpq_status run_fused_batch(const std::vector<const cfpq_graph_s *> &gs, const s
     // after the staging copy on the same stream: the pinned area is free
     HIP_TRY(hipMemcpy2DAsync(h, kBatchStatWords * 8, wk + o_stats, stat_pitch * 8, kBatchStatWords * 8, k,
                              hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(wait_stream(s));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, evp.v[0], evp.v[1]));
     const unsigned long long *st = pin.h;
@@ -2344,7 +2362,7 @@ extern "C" cfpq_status cfpq_query_noalloc(cfpq_graph g, cfpq_rsm r, uint32_t box
         unsigned long long stats[2] = {0, 0}, cnt = 0;
         HIP_TRY(hipMemcpyAsync(stats, q.stats, sizeof(stats), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&cnt, count, sizeof(cnt), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(wait_stream(s));
         if (stats[1] != 0) return fail(CFPQ_ERR_LIMIT, "fixpoint did not stop");
         if (pairs) *pairs = cnt;
         if (iterations) *iterations = (uint32_t)stats[0];
