@@ -950,6 +950,9 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     if (use_sum) {
         if (!dsum.alloc(al, (uint64_t)nB * n * sum_pitch * 8, s))
             return fail(CFPQ_ERR_OOM, "device allocation failed (selector summary)");
+        // zero first: the write-back rewrites a row's summary only in the
+        // blocks it visits
+        HIP_TRY(launch_fill(dsum.as<uint64_t>(), (uint64_t)nB * n * sum_pitch, 0, s));
         HIP_TRY(launch_row_summary(d_dNT, nB, n, P, Pn, dact[cur], dsum.as<uint64_t>(), sum_pitch, s));
     }
 
@@ -1008,6 +1011,22 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
     const uint64_t seed_ell_bytes = al256b((ell_pad + (uint64_t)nQ * n * kEll) * 4);
     const uint64_t seed_tile_bytes = seed_ell_bytes + al256b(dense_words * 8);
     bool keep_ell = CFPQ_SEED_ELL_KEEP && sparse_nt && !scratch && (uint64_t)groups * seed_tile_bytes <= (8ull << 30);
+    // changed blocks: the gathers mark per T row the blocks of blk_words
+    // words that gained bits (at most 64 blocks a row), the write-back keeps
+    // per dNT row the blocks holding bits, and visits only those blocks
+#ifndef CFPQ_WB_BLOCKS
+#define CFPQ_WB_BLOCKS 1
+#endif
+    const bool wb_blocks = CFPQ_WB_BLOCKS != 0;
+    uint32_t blk_shift = 6;   // blocks of 2^blk_shift words, at most 64 of them a row
+    while (((uint64_t)Pn + (1ull << blk_shift) - 1) >> blk_shift > 64) ++blk_shift;
+    const uint32_t blk_words = 1u << blk_shift;
+    DevBuf blk_buf;
+    if (wb_blocks && !blk_buf.alloc(al, ((uint64_t)nQ * n + (uint64_t)nB * n) * 8, s))
+        return fail(CFPQ_ERR_OOM, "device allocation failed (changed blocks)");
+    uint64_t *d_chgb = wb_blocks ? blk_buf.as<uint64_t>() : nullptr;
+    uint64_t *d_dnb = wb_blocks ? d_chgb + (uint64_t)nQ * n : nullptr;
+    if (wb_blocks) HIP_TRY(launch_fill(d_dnb, (uint64_t)nB * n, 0, s));
     DevBuf seed_buf, chg_prev_buf;
     if (keep_ell && (!seed_buf.alloc(al, groups * seed_tile_bytes, s) || !chg_prev_buf.alloc(al, aw * 8, s)))
         return fail(CFPQ_ERR_OOM, "device allocation failed (seed lists)");
@@ -1057,6 +1076,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         }
         if (keep_ell) std::swap(d_chg, d_chg_prev);   // the last iteration's changes pick the lists to rebuild
         HIP_TRY(launch_fill(d_chg, aw, 0, s));   // rows gaining bits in this iteration
+        if (wb_blocks) HIP_TRY(launch_fill(d_chgb, (uint64_t)nQ * n, 0, s));   // and their blocks
         if (scratch && it > 1) {   // forget the closure: only the box-start rows' own bits
             HIP_TRY(launch_fill(d_T, qw, 0, s));
             HIP_TRY(launch_fill(tnz.as<uint64_t>(), aw, 0, s));
@@ -1073,6 +1093,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             a.in_off = tb.in_off; a.in_tr = tb.in_tr;
             a.T = d_T; a.tnz = tnz.as<uint64_t>(); a.ctr = d_ctr; a.clear_words = (uint32_t)aset;
             a.Pbs = Pbs; a.chg = d_chg;
+            a.chgb = d_chgb; a.blk_shift = blk_shift;
             // Kronecker product of the RSM with the new edges (seed); the seed
             // and the first chunk of levels always fit before a ring clear
             if ((st = need_slots(levels_hint + 2)) != CFPQ_OK) return st;
@@ -1271,6 +1292,11 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
             w.nsum = use_nsum ? nsum.as<uint64_t>() : nullptr;
         }
         w.dhash = dedup ? dd_hash : nullptr;
+        // whole rows in the first iteration (its seed writes T outside the
+        // gathers) and when the closure is recomputed
+        w.chgb = (wb_blocks && it > 1 && !scratch) ? d_chgb : nullptr;
+        w.dnb = d_dnb;
+        w.blk_words = blk_words;
         if ((st = prof_mark(0)) != CFPQ_OK) return st;
         HIP_TRY(launch_writeback(w, gather_grid((uint64_t)nB * n), s));
         if ((st = prof_mark(1)) != CFPQ_OK) return st;

@@ -88,6 +88,10 @@ struct GatherArgs {
     // representatives only, and (f, v) reads the row of (f, rep).  null = off
     const uint32_t *rep;
     const uint32_t *f_box;
+    // optional: per row [nQ][n] a mask of the blocks of 2^blk_shift words of
+    // T that gained bits in this iteration (bit b: words b 2^blk_shift ..)
+    uint64_t *chgb;
+    uint32_t blk_shift;
 };
 constexpr uint32_t kNoBox = 0xFFFFFFFFu;
 // summary of the rows [nB][n][P] whose bit is set in act ([nB][Pn] bits;
@@ -147,6 +151,16 @@ struct WritebackArgs {
     // optional: per row [nB][n] a 64-bit hash of its new edges (dNT row),
     // written for rows that gained edges (non-zero)
     uint64_t *dhash;
+    // optional (levels strategy): chgb, the gathers' masks of the T blocks
+    // that gained bits ([nQ][n], blocks of blk_words words), and dnb, per row
+    // [nB][n] the blocks where dNT is non-zero (written here).  With chgb a
+    // visited row is processed only in the blocks some final-state row
+    // gained bits in or its dNT row held bits in: elsewhere NT cannot gain
+    // and dNT, its summary and NT's summary are already what the write-back
+    // would leave.  Without chgb rows are processed whole (dnb still written)
+    const uint64_t *chgb;
+    uint64_t *dnb;
+    uint32_t blk_words;
 };                                 // dNT / dnt_act may be null (no delta kept)
 
 // kernels.hip

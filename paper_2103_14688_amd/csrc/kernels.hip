@@ -274,10 +274,11 @@ __device__ __forceinline__ void or_row(uint64_t (&acc)[kChunks], const uint64_t 
 // new bits to cnt (per lane); fed tells whether any source row fed the row.
 template <bool SEED>
 __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned long long &cnt,
-                           bool &fed, unsigned long long &by) {
+                           bool &fed, unsigned long long &by, uint64_t &blocks) {
     const int lane = __lane_id();
     const uint32_t tb = a.in_off[f], te = a.in_off[f + 1];
     fed = false;
+    blocks = 0;   // the T blocks that gained bits (wave-uniform)
     if (tb == te) return false;
     bool row_new = false;
     for (uint32_t pass0 = 0; pass0 < a.gw; pass0 += kChunks * kWave) {
@@ -364,9 +365,10 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             const uint32_t w = pass0 + c * kWave + lane;
+            uint64_t nw = 0;
             if (w < a.gw) {
                 const uint64_t t = trow[c * kWave + lane];
-                const uint64_t nw = acc[c] & ~t;
+                nw = acc[c] & ~t;
                 if (nw) {
                     trow[c * kWave + lane] = t | nw;
                     any = true;
@@ -374,6 +376,18 @@ __device__ bool gather_row(const GatherArgs &a, uint32_t f, uint32_t v, unsigned
                 }
                 drow[c * kWave + lane] = nw;
                 by += nw ? 24 : 16;   // T read, frontier written, T written if it grew
+            }
+            if (a.chgb) {
+                // the blocks of the chunk's words that grew (a chunk of 64
+                // words meets at most two blocks): wave-uniform
+                const uint64_t bal = __ballot(nw != 0);
+                if (bal) {
+                    const uint32_t base = a.w0 + pass0 + (uint32_t)c * kWave;
+                    const uint32_t b0 = base >> a.blk_shift, b1 = (base + kWave - 1) >> a.blk_shift;
+                    const uint64_t lo = b0 == b1 ? ~0ull : (1ull << ((b1 << a.blk_shift) - base)) - 1ull;
+                    if (bal & lo) blocks |= 1ull << (b0 & 63u);
+                    if (bal & ~lo) blocks |= 1ull << (b1 & 63u);
+                }
             }
         }
         row_new |= (__ballot(any) != 0);
@@ -942,7 +956,9 @@ __global__ __launch_bounds__(kBlock, CFPQ_GATHER_MIN_WAVES) void k_gather(Gather
     for (uint64_t r = wave; r < rows; r += nwaves) {
         const uint32_t f = (uint32_t)(r / a.n), v = (uint32_t)(r % a.n);
         bool fed = false;
-        if (gather_row<SEED>(a, f, v, cnt, fed, by) && lane == 0) {
+        uint64_t blocks = 0;
+        if (gather_row<SEED>(a, f, v, cnt, fed, by, blocks) && lane == 0) {
+            if (a.chgb && blocks) atomicOr((unsigned long long *)&a.chgb[r], (unsigned long long)blocks);
             atomicOr((unsigned long long *)&a.actn[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
             atomicOr((unsigned long long *)&a.tnz[(uint64_t)f * a.Pn + (v >> 6)], 1ull << (v & 63));
             if (a.actn_blk) mark_blk(a.actn_blk, a.Pbs, f, v);
@@ -981,8 +997,11 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
     uint64_t *dnt = a.dNT ? a.dNT + ((uint64_t)N * a.n + v) * a.P : nullptr;
     bool any = false;
     unsigned long long hs = 0;   // hash of the new edges: sum over non-zero words of a mix of (word, index)
+    uint64_t dblocks = 0;        // blocks of the new dNT row holding bits
     const uint32_t nch = cond_chunks(a.Pn), cwds = cond_chunk_words(a.Pn);
-    for (uint32_t k = lane; k < a.Pn; k += kWave) {
+    // word k of the row (lanes of one 64-word group together: lane l takes
+    // word 64 i + l)
+    auto word = [&](uint32_t k) {
         uint64_t acc = 0;
         for (uint32_t i = fb; i < fe; ++i) {
             const uint64_t node = (uint64_t)a.fin[i] * a.n + v;
@@ -1009,16 +1028,34 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
             }
         }
         if (dnt) dnt[k] = nw;
+        const uint64_t dm = __ballot(nw != 0);
+        const uint32_t g = (k - (uint32_t)lane) / kWave;   // the 64-word group
+        if (a.dnb && dm) dblocks |= 1ull << (((uint64_t)g * kWave / a.blk_words) & 63u);
         if (a.dsum || a.nsum) {
-            // lane l holds word 64 i + l: one summary word per step
-            const uint64_t dm = __ballot(nw != 0), nm = __ballot((old | nw) != 0);
-            const uint64_t so = ((uint64_t)N * a.n + v) * a.sum_pitch + (k - (uint32_t)lane) / kWave;
+            // one summary word per group
+            const uint64_t nm = __ballot((old | nw) != 0);
+            const uint64_t so = ((uint64_t)N * a.n + v) * a.sum_pitch + g;
             if (lane == 0) {
                 if (a.dsum) a.dsum[so] = dm;
                 if (a.nsum) a.nsum[so] = nm;
             }
         }
+    };
+    if (a.chgb) {
+        // the blocks where a final-state row gained bits or dNT held bits
+        uint64_t blocks = a.dnb ? a.dnb[(uint64_t)N * a.n + v] : 0ull;
+        for (uint32_t i = fb; i < fe; ++i) blocks |= a.chgb[(uint64_t)a.fin[i] * a.n + v];
+        while (blocks) {
+            const uint32_t b = (uint32_t)__ffsll((unsigned long long)blocks) - 1;
+            blocks &= blocks - 1;
+            const uint32_t k1 = (b + 1) * a.blk_words < a.Pn ? (b + 1) * a.blk_words : a.Pn;
+            for (uint32_t k0 = b * a.blk_words; k0 < k1; k0 += kWave)
+                if (k0 + (uint32_t)lane < k1) word(k0 + (uint32_t)lane);
+        }
+    } else {
+        for (uint32_t k = lane; k < a.Pn; k += kWave) word(k);
     }
+    if (a.dnb && lane == 0) a.dnb[(uint64_t)N * a.n + v] = dblocks;
     any_row = __ballot(any) != 0;
     if (a.dhash && any_row) {
         hs = wave_sum(hs);
@@ -1472,6 +1509,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     a.dense_apart = 0;
     a.rep = nullptr;
     a.f_box = nullptr;
+    a.chgb = nullptr;
+    a.blk_shift = 6;
 
     WritebackArgs wb;
     wb.n = Q.n; wb.P = Q.P; wb.Pn = Q.Pn; wb.nB = Q.nB; wb.fin_off = Q.fin_off; wb.fin = Q.fin;
@@ -1480,6 +1519,7 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
     wb.state_flags = nullptr; wb.multi = nullptr; wb.skip_if[0] = wb.skip_if[1] = nullptr;
     wb.chg = nullptr; wb.prev_act = nullptr; wb.rows_ctr = nullptr;
     wb.dsum = nullptr; wb.nsum = nullptr; wb.sum_pitch = 0; wb.dhash = nullptr;
+    wb.chgb = nullptr; wb.dnb = nullptr; wb.blk_words = kWave;
 
     uint64_t *D = Q.D, *Dn = Q.Dn, *act = Q.act, *actn = Q.actn;
     const bool narrow = Q.Pn <= kNarrowWords;
@@ -1516,7 +1556,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
                 const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
                 bool fed;
                 unsigned long long by = 0;
-                if (gather_row<true>(a, f, v, cnt, fed, by) && lane == 0) {
+                uint64_t blocks = 0;
+                if (gather_row<true>(a, f, v, cnt, fed, by, blocks) && lane == 0) {
                     atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                     atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                 }
@@ -1549,7 +1590,8 @@ __device__ void run_fused(const FusedQuery &Q, unsigned long long *s_cnt,
                     const uint32_t f = (uint32_t)(r / Q.n), v = (uint32_t)(r % Q.n);
                     bool fed;
                     unsigned long long by = 0;
-                    if (gather_row<false>(a, f, v, cnt, fed, by) && lane == 0) {
+                    uint64_t blocks = 0;
+                    if (gather_row<false>(a, f, v, cnt, fed, by, blocks) && lane == 0) {
                         atomicOr((unsigned long long *)&actn[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                         atomicOr((unsigned long long *)&Q.tnz[(uint64_t)f * Q.Pn + (v >> 6)], 1ull << (v & 63));
                     }
