@@ -360,8 +360,10 @@ void cfpq_paths_close(cfpq_paths it);
  *     8 * tile_words * (R_in + 3 * R_out), R_in the frontier rows read and
  *     R_out the target rows fed by them (read T, write T and the next
  *     frontier);
- *   CFPQ_KERNEL_WRITEBACK: 8 * ceil(n/64) * (|F_N| + 3) per row of box N it
- *     visits (rows whose final-state closure rows changed in the iteration);
+ *   CFPQ_KERNEL_WRITEBACK: 8 * (|F_N| + 3) per word of the rows of box N it
+ *     processes (rows whose final-state closure rows changed in the
+ *     iteration; from the second iteration on only the 64-word blocks where
+ *     a final-state row gained bits or the A2^N row held bits);
  *   CFPQ_KERNEL_COND_LEVEL: one topological level of the component graph,
  *     8 bytes per word of component rows it writes (answer rows in full,
  *     other rows only in their non-empty chunks, a row cut into

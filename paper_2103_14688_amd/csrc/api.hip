@@ -1337,12 +1337,12 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         res.prof[CFPQ_KERNEL_NT_MFMA].bytes = pc2[0] * 65536ull;   // 2 * 32 * 32 * 32 per instruction
         res.prof[CFPQ_KERNEL_NT_SPARSE].bytes = pc2[1];
         res.prof[CFPQ_KERNEL_NT_DENSE].bytes = pc2[2];
-        // write-back: per row visited, the final states' closure rows and
-        // the M2^N row read, M2^N and A2^N written (Pn words each)
+        // write-back: per row word processed, the final states' closure
+        // words and the M2^N word read, M2^N and A2^N words written
         auto &pw = res.prof[CFPQ_KERNEL_WRITEBACK];
         pw.bytes = 0;
         for (uint32_t b = 0; b < nB; ++b)
-            pw.bytes += pc2[3 + b] * 8ull * Pn * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + 3);
+            pw.bytes += pc2[3 + b] * 8ull * (uint64_t)(p.fin_off[b + 1] - p.fin_off[b] + 3);
     }
     if (o.keep_blocks) res.T = std::move(T);
     return CFPQ_OK;

@@ -142,7 +142,7 @@ struct WritebackArgs {
     // every other row of NT and dNT is already what the write-back would leave
     const uint64_t *chg;
     const uint64_t *prev_act;
-    unsigned long long *rows_ctr;  // optional (profiling): rows visited, per box [nB]
+    unsigned long long *rows_ctr;  // optional (profiling): row words processed, per box [nB]
     // optional: summaries of the visited rows ([nB][n][sum_pitch], bit w % 64
     // of word w / 64 set iff word w is non-zero) of dNT and NT, written here
     // instead of by a separate pass over the rows

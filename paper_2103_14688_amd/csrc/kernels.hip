@@ -989,8 +989,10 @@ hipError_t launch_gather(const GatherArgs &a, bool seed, uint32_t grid, hipStrea
 // closure entry from (q_N^0, u) to (f, v), f final in box N, become edges of
 // M2^N; those not already present form A2^N for the next iteration.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N, uint32_t v,
-                                              unsigned long long &cnt_box, bool &any_row) {
+// returns the words of the row it processed (all Pn, or those of the blocks
+// it visits)
+__device__ __forceinline__ uint32_t writeback_row(const WritebackArgs &a, uint32_t N, uint32_t v,
+                                                  unsigned long long &cnt_box, bool &any_row) {
     const int lane = __lane_id();
     const uint32_t fb = a.fin_off[N], fe = a.fin_off[N + 1];
     uint64_t *nt = a.NT + ((uint64_t)N * a.n + v) * a.P;
@@ -1041,14 +1043,17 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
             }
         }
     };
+    uint32_t words = a.Pn;
     if (a.chgb) {
         // the blocks where a final-state row gained bits or dNT held bits
+        words = 0;
         uint64_t blocks = a.dnb ? a.dnb[(uint64_t)N * a.n + v] : 0ull;
         for (uint32_t i = fb; i < fe; ++i) blocks |= a.chgb[(uint64_t)a.fin[i] * a.n + v];
         while (blocks) {
             const uint32_t b = (uint32_t)__ffsll((unsigned long long)blocks) - 1;
             blocks &= blocks - 1;
             const uint32_t k1 = (b + 1) * a.blk_words < a.Pn ? (b + 1) * a.blk_words : a.Pn;
+            words += k1 - b * a.blk_words;
             for (uint32_t k0 = b * a.blk_words; k0 < k1; k0 += kWave)
                 if (k0 + (uint32_t)lane < k1) word(k0 + (uint32_t)lane);
         }
@@ -1061,6 +1066,7 @@ __device__ __forceinline__ void writeback_row(const WritebackArgs &a, uint32_t N
         hs = wave_sum(hs);
         if (lane == 0) a.dhash[(uint64_t)N * a.n + v] = hs ? hs : 1ull;
     }
+    return words;
 }
 
 constexpr uint32_t kWbLdsBoxes = 64;   // boxes whose new-edge counts gather in LDS first
@@ -1089,13 +1095,13 @@ __global__ __launch_bounds__(kBlock, CFPQ_WB_MIN_WAVES) void k_writeback(Writeba
         }
         unsigned long long c = 0;
         bool any = false;
-        writeback_row(a, N, v, c, any);
+        const uint32_t words = writeback_row(a, N, v, c, any);
         c = wave_sum(c);
-        if (a.rows_ctr && lane == 0) {
+        if (a.rows_ctr && lane == 0) {   // profiling: row words processed
             if (lds_boxes)
-                atomicAdd(&s_rows[N], 1ull);
+                atomicAdd(&s_rows[N], (unsigned long long)words);
             else
-                atomicAdd(&a.rows_ctr[N], 1ull);
+                atomicAdd(&a.rows_ctr[N], (unsigned long long)words);
         }
         if (lane == 0 && any) {
             if (a.dnt_act)
