@@ -55,11 +55,17 @@ typedef struct cfpq_result_s *cfpq_result;
  * to 256 bytes (as hipMalloc's; a less aligned block is handed back to free
  * and the call fails with CFPQ_ERR_OOM); free receives the pointer and size
  * that alloc produced.  Both are called with the stream the memory is used
- * on. */
+ * on.  cached may be NULL; otherwise it returns the bytes the allocator holds
+ * unused and can hand out again (a caching allocator's free blocks, which
+ * the device does not count as free): a query that sizes its buffers by the
+ * device's free memory (the source tiles of CFPQ_STRATEGY_LEVELS) counts
+ * them too.  Without it, memory such an allocator keeps from earlier calls
+ * shrinks those tiles, down to one word. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *stream, void *ctx);
     void (*free)(void *ptr, size_t bytes, void *stream, void *ctx);
     void *ctx;
+    size_t (*cached)(void *ctx);
 } cfpq_allocator;
 
 /* ------------------------------------------------------------------------

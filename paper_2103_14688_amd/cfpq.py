@@ -42,10 +42,11 @@ class CfpqError(RuntimeError):
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_CACHED_FN = ctypes.CFUNCTYPE(ctypes.c_size_t, ctypes.c_void_p)
 
 
 class Allocator(ctypes.Structure):
-    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p), ("cached", _CACHED_FN)]
 
 
 class QueryOpts(ctypes.Structure):
@@ -143,7 +144,16 @@ def torch_allocator():
             except Exception:
                 pass
 
-        a = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
+        def _cached(ctx):
+            # reserved but unallocated: torch hands these blocks out again,
+            # and releases them to the device when an allocation needs them
+            try:
+                dev = torch.cuda.current_device()
+                return max(0, torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev))
+            except Exception:
+                return 0
+
+        a = Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None, _CACHED_FN(_cached))
         _torch_alloc = a
     return _torch_alloc
 

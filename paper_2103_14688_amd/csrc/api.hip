@@ -65,6 +65,8 @@ struct Alloc {
         if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
         return p;
     }
+    // bytes the hooks hold unused and can hand out again (0 without hooks)
+    size_t cached() const { return has && a.cached ? a.cached(a.ctx) : 0; }
     void put(void *p, size_t bytes, hipStream_t s) const {
         if (!p) return;
         if (!bytes) bytes = 8;
@@ -786,6 +788,7 @@ cfpq_status run_levels(const cfpq_graph_s &g, const cfpq_rsm_s &r, const cfpq_qu
         if (!p.nt_src.empty() && o.nt_mode != CFPQ_NT_ROWS) G = std::min<uint32_t>(G, kTileCapWords);
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+            free_b += al->cached();   // a caching allocator's free blocks are free for this query too
             const double fixed = 8.0 * ((double)qw + 2.0 * (double)bw) + 4.0 * nQ * (double)n * (kEll + 1) +
                                  16.0 * nB * (double)n * ((Pn + 63) / 64) + (o.keep_rank ? (double)nB * n * n : 0.0) +
                                  (256.0 * (1 << 20));

@@ -17,6 +17,7 @@ is compared by (count, hash).
                            edges: the closed form (all pairs of vertices of
                            equal depth >= 1; Sec. 4.2 query on a tree),
                            counted and hashed group by group.
+  samegen_typefree_n500000 the same at n = 500,000 (the largest hierarchy).
   alias_n20000             memory alias MA on the clustered graph
                            n = 20,000 (clusters of 64..512 vertices):
                            semi-naive rounds; both nonterminals.
@@ -99,13 +100,12 @@ def samegen(threads, which):
     return _grammar_entry(g, text, "synth.hierarchy(50000, seed=BASE_SEED + 3)", threads)
 
 
-def samegen_typefree(threads):
-    n = 200000
+def samegen_typefree(threads, n=200000):
     g, depth = synth.hierarchy(n, with_type=False, seed=synth.BASE_SEED + 3)
     groups = [np.flatnonzero(depth == d).astype(np.uint32) for d in range(1, int(depth.max()) + 1)]
     t = time.time()
     c, h = oracle.groups_hash(groups, threads=threads)
-    return {"graph": "synth.hierarchy(200000, with_type=False, seed=BASE_SEED + 3)", "query": synth.SAME_GEN_G1,
+    return {"graph": f"synth.hierarchy({n}, with_type=False, seed=BASE_SEED + 3)", "query": synth.SAME_GEN_G1,
             "boxes": {"S": {"count": c, "hash": _hex(h)}},
             "oracle": "closed form: pairs of vertices of equal depth >= 1 (groups_hash)",
             "levels": [len(x) for x in groups], "seconds": round(time.time() - t, 1)}
@@ -196,6 +196,7 @@ JOBS = {
     "samegen_g1_n50000": lambda th: samegen(th, "g1"),
     "samegen_g2_n50000": lambda th: samegen(th, "g2"),
     "samegen_typefree_n200000": samegen_typefree,
+    "samegen_typefree_n500000": lambda th: samegen_typefree(th, 500000),
     "alias_n20000": alias,
     "serving": serving,
 }

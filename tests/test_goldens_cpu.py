@@ -24,9 +24,11 @@ def test_rpq_blocks_add_up(gold):
     assert len(g["blocks"]) * g["block_sources"] == 100000
 
 
-def test_typefree_closed_form_count(gold):
-    e = gold["samegen_typefree_n200000"]
+@pytest.mark.parametrize("n", [200000, 500000])
+def test_typefree_closed_form_count(gold, n):
+    e = gold[f"samegen_typefree_n{n}"]
     assert e["boxes"]["S"]["count"] == sum(x * x for x in e["levels"])
+    assert sum(e["levels"]) < n
 
 
 def test_serving_subset_covers_the_definition(gold):

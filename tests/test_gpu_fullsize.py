@@ -9,7 +9,8 @@ splitmix64((u << 32) | v) over the pairs.
   strategy and three automata for (a|b)* c d* (minimal 2 states, the
   unminimised 5-state Glushkov automaton, a 4-state one given state by state);
 * same-generation G1 and G2 on the hierarchy n = 50,000 with type edges, and
-  G1 without type edges at n = 200,000 (closed form);
+  G1 without type edges at n = 200,000 and n = 500,000 (closed form; the
+  larger one runs in source tiles and with write-back blocks of 128 words);
 * memory alias on the clustered graph n = 20,000 with 64..512-vertex
   clusters, both nonterminals.
 """
@@ -126,3 +127,25 @@ def test_alias_clustered_n20000(gold):
     res = cfpq.query(graph, cfpq.Query(R))
     for name, w in want["boxes"].items():
         _same(res, R.box(name), w)
+
+
+def test_samegen_typefree_closed_form_n500000(gold):
+    # the largest hierarchy: a 187 GB closure, so the sources go in tiles,
+    # and rows of 7,813 words, so the write-back's blocks are 128 words
+    import gc
+    import torch
+    print("fullsize: same generation G1 without type edges n=500000 (closed form)", flush=True)
+    want = gold["samegen_typefree_n500000"]["boxes"]["S"]
+    _graphs.clear()
+    gc.collect()
+    torch.cuda.empty_cache()
+    g, graph = _graph("samegen500k",
+                      lambda: synth.hierarchy(500000, with_type=False, seed=synth.BASE_SEED + 3)[0])
+    R = rsm_mod.from_grammar(synth.SAME_GEN_G1, g.labels)
+    res = cfpq.query(graph, cfpq.Query(R))
+    try:
+        _same(res, 0, want)
+    finally:
+        del res
+        _graphs.clear()
+        gc.collect()

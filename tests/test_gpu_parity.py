@@ -543,6 +543,40 @@ def test_large_same_generation_selector_summary():
     assert rows.stats()[:2] == res.stats()[:2] and rows.hash(0) == res.hash(0)
 
 
+def test_source_tiles_count_cached_allocator_memory():
+    # the source tiles are as wide as the memory a query can get allows:
+    # blocks that torch's caching allocator keeps unused count (it hands
+    # them out again), although the device reports them as taken.  With
+    # nearly all device memory parked in the cache the query still runs in
+    # one tile: the seed launches once per iteration, as with an empty cache
+    import gc
+    import torch
+    g = synth.hierarchy(50000, seed=synth.BASE_SEED + 3)[0]
+    R = rsm_mod.from_grammar(synth.SAME_GEN_G1, g.labels)
+    graph = cfpq.Graph.from_synth(g)
+    q = cfpq.Query(R)
+    gc.collect()
+    torch.cuda.empty_cache()
+    ref = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, profile=True)
+    seeds = ref.profile(cfpq.KERNEL_SEED)[0]
+    assert 0 < seeds <= ref.stats()[0]   # one tile: at most one seed per iteration
+    free, _ = torch.cuda.mem_get_info()
+    hold = free - (4 << 30)
+    if hold <= 0:
+        pytest.skip("less than 4 GiB of device memory free")
+    parked = torch.empty(hold, dtype=torch.uint8, device="cuda")
+    del parked   # back in the cache: the device no longer counts it as free
+    try:
+        res = cfpq.query(graph, q, strategy=cfpq.STRATEGY_LEVELS, profile=True)
+        assert res.profile(cfpq.KERNEL_SEED)[0] == seeds
+        assert res.stats()[:2] == ref.stats()[:2]
+        assert (res.count(0), res.hash(0)) == (ref.count(0), ref.hash(0))
+        del res
+    finally:
+        gc.collect()
+        torch.cuda.empty_cache()
+
+
 # closure recomputed from scratch each iteration (the variant the paper
 # evaluated) against the incremental closure: same relation, iterations and
 # per-iteration counts; one case also against the oracle
