@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # of 18 productive level launches each; the grammar blocks: every launch of
 # the block's runs, without the autotuner's).
 PMC_TRAFFIC = {
-    ("0c82ca3cbf768d34", "rpq_powerlaw_n100000", "k_cond_level"): 101209234,
-    ("0c82ca3cbf768d34", "samegen_n200000", "k_nt_sparse"): 499031347,
-    ("0c82ca3cbf768d34", "alias_n20000", "k_nt_dense"): 76439245,
-    ("0c82ca3cbf768d34", "samegen_n50000", "k_writeback"): 232384922,
+    ("42c7087aab9f7720", "rpq_powerlaw_n100000", "k_cond_level"): 101210941,
+    ("42c7087aab9f7720", "samegen_n200000", "k_nt_sparse"): 498617806,
+    ("42c7087aab9f7720", "alias_n20000", "k_nt_dense"): 76436347,
+    ("42c7087aab9f7720", "samegen_n50000", "k_writeback"): 232384853,
 }
 
 
