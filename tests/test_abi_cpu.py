@@ -31,6 +31,30 @@ def test_library_exports_every_declared_symbol():
     assert cfpq.cfpq_version().startswith("cfpq-gfx950")
 
 
+def _header_struct_fields(name):
+    """Field names, in order, of `typedef struct { ... } name;` in the header."""
+    text = open(os.path.join(ROOT, "include", "cfpq.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ptr = re.search(r"\(\s*\*\s*(\w+)\s*\)", decl)   # function pointer
+        fields.append(ptr.group(1) if ptr else re.findall(r"\w+", decl)[-1])
+    return fields
+
+
+@pytest.mark.parametrize("cname, pytype", [("cfpq_allocator", "Allocator"), ("cfpq_query_opts", "QueryOpts")])
+def test_binding_structs_mirror_the_header(cname, pytype):
+    # the ctypes structures the binding passes across the boundary list the
+    # header's fields in the header's order (a missing or moved field would
+    # be read as another one by the library)
+    got = [f[0] for f in getattr(cfpq, pytype)._fields_]
+    assert got == _header_struct_fields(cname)
+
+
 def test_rsm_validation_errors():
     ok = dict(n_states=2, n_terminals=1, n_boxes=1, box_start=[0], state_box=[0, 0], is_final=[0, 1],
               t_src=[0], t_sym=[0], t_dst=[1])
