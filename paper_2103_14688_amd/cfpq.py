@@ -145,11 +145,13 @@ def torch_allocator():
                 pass
 
         def _cached(ctx):
-            # reserved but unallocated: torch hands these blocks out again,
-            # and releases them to the device when an allocation needs them
+            # reserved but unallocated, less the free pieces of segments that
+            # still hold live blocks: what torch hands out again, or releases
+            # to the device when an allocation needs it
             try:
-                dev = torch.cuda.current_device()
-                return max(0, torch.cuda.memory_reserved(dev) - torch.cuda.memory_allocated(dev))
+                st = torch.cuda.memory_stats(torch.cuda.current_device())
+                free_blocks = st.get("reserved_bytes.all.current", 0) - st.get("allocated_bytes.all.current", 0)
+                return max(0, free_blocks - st.get("inactive_split_bytes.all.current", 0))
             except Exception:
                 return 0
 
